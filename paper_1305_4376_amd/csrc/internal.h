@@ -1,0 +1,31 @@
+// internal.h -- declarations shared by libtdes's translation units (not part of the ABI).
+#pragma once
+#include <stdint.h>
+#include <hip/hip_runtime.h>
+
+#include "../../include/tdes.h"
+
+namespace tdes {
+
+// Words of a schedule: encryption rounds first, then decryption rounds.
+// Round r of a direction uses words 2r (boxes 1,7,5,3 chunks) and 2r+1.
+constexpr int kRounds = 48;
+constexpr int kDirWords = 2 * kRounds;
+
+// Per-device properties the launchers need (cached on first use).
+struct DeviceInfo {
+    int cu_count;
+    int device;
+};
+int device_info(DeviceInfo *info);
+
+// Kernel launchers.  Arguments are already validated; n_blocks > 0.
+// `ks` points at the 96 words of one direction.
+hipError_t launch_table(const uint32_t *ks, const uint8_t *in, uint8_t *out, uint64_t n_blocks,
+                        hipStream_t stream);
+hipError_t launch_bitslice(const uint32_t *ks, const uint8_t *in, uint8_t *out, uint64_t n_blocks,
+                           hipStream_t stream);
+hipError_t launch_fill_splitmix64(uint64_t *dev, uint64_t n_words, uint64_t seed, uint64_t first,
+                                  hipStream_t stream);
+
+}  // namespace tdes

@@ -1,0 +1,41 @@
+// k_util.hip -- device-side SplitMix64 fill (synthetic messages made in place in HBM).
+//
+// Word i of the stream seeded with s is mix(s + (i + 1) * 0x9E3779B97F4A7C15),
+// the SplitMix64 output function (Steele, Lea and Flood, OOPSLA 2014).
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ uint64_t splitmix64_word(uint64_t seed, uint64_t i) {
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(kThreads) void fill_kernel(uint64_t *dev, uint64_t n, uint64_t seed, uint64_t first) {
+    const uint64_t stride = (uint64_t)gridDim.x * kThreads;
+    for (uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride)
+        dev[i] = splitmix64_word(seed, first + i);
+}
+
+}  // namespace
+
+namespace tdes {
+
+hipError_t launch_fill_splitmix64(uint64_t *dev, uint64_t n_words, uint64_t seed, uint64_t first,
+                                  hipStream_t stream) {
+    DeviceInfo info;
+    if (device_info(&info) != TDES_OK) return hipErrorInvalidDevice;
+    uint64_t grid = (n_words + kThreads - 1) / kThreads;
+    const uint64_t cap = (uint64_t)info.cu_count * 16;
+    if (grid > cap) grid = cap;
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)grid), dim3(kThreads), 0, stream, dev, n_words, seed, first);
+    return hipGetLastError();
+}
+
+}  // namespace tdes

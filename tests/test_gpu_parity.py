@@ -1,0 +1,168 @@
+"""GPU parity: libtdes's kernels against the oracle, bit for bit (tolerance: 0 bits).
+
+Every message block is enciphered on its own (ECB, Abstract) by E-D-E under
+K1, K2, K3 and decrypted in reverse (Section II.A).  Sizes span several tiles
+and ragged tails; the full 1 GiB message runs in the benchmark's launch
+configuration and is checked on sampled blocks, which the oracle computes one
+by one, plus the round trip at full size.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1305_4376_amd as td
+from paper_1305_4376_amd import inputs
+from tests import _gpu
+from tests._gpu import DEV
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = [td.TDES_VARIANT_TABLE, td.TDES_VARIANT_AUTO]
+DIRS = [td.TDES_ENCRYPT, td.TDES_DECRYPT]
+
+EDGE_SIZES = [1, 2, 3, 31, 32, 33, 63, 64, 65, 127, 128, 129, 511, 512, 513, 2047, 2048, 2049, 4095, 4097,
+              65535, 65537, 131071]
+
+
+def _check_full(keys, n, variant, direction, data_seed, offset=0, in_place=False):
+    host = inputs.message(data_seed, n)
+    sched = _gpu.device_sched(*keys)
+    src = _gpu.to_device(host, offset)
+    dst = src if in_place else _gpu.empty_like_dev(8 * n, offset)
+    print(f"[parity] n={n} variant={variant} dir={direction} offset={offset} in_place={in_place}", flush=True)
+    _gpu.run(sched, src, dst, n, direction, variant)
+    got = dst.cpu().numpy()
+    want = _gpu.oracle_on_blocks(keys, host, decrypt=direction == td.TDES_DECRYPT)
+    assert np.array_equal(got, want), f"first mismatch at block {np.argmax((got != want).reshape(-1, 8).any(1))}"
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_c1_one_mib_encrypt_then_decrypt(variant):
+    """One 1 MiB message (131072 blocks), a random three-key triple with odd parity."""
+    n = 131072
+    keys = inputs.key_triple(inputs.KEY_SEED_BASE + 0)
+    host = inputs.message(inputs.DATA_SEED_BASE + 0, n)
+    sched = _gpu.device_sched(*keys)
+    src = _gpu.to_device(host)
+    ct = _gpu.empty_like_dev(8 * n)
+    pt = _gpu.empty_like_dev(8 * n)
+    print(f"[parity] C1 variant={variant}", flush=True)
+    _gpu.run(sched, src, ct, n, td.TDES_ENCRYPT, variant)
+    _gpu.run(sched, ct, pt, n, td.TDES_DECRYPT, variant)
+    want = _gpu.oracle_on_blocks(keys, host, decrypt=False)
+    assert np.array_equal(ct.cpu().numpy(), want)
+    assert np.array_equal(pt.cpu().numpy(), host)
+    assert np.array_equal(_gpu.oracle_on_blocks(keys, want, decrypt=True), host)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("direction", DIRS)
+def test_edge_sizes(variant, direction):
+    keys = inputs.key_triple(0x801)
+    for i, n in enumerate(EDGE_SIZES):
+        _check_full(keys, n, variant, direction, 0x900 + i)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("keying", [1, 2, 3])
+def test_keying_options(variant, keying):
+    keys = inputs.key_triple(0x810 + keying, keying)
+    for direction in DIRS:
+        _check_full(keys, 3000, variant, direction, 0x910 + keying)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_misaligned_and_in_place(variant):
+    keys = inputs.key_triple(0x820)
+    # 8-byte but not 16-byte aligned buffers take the narrow load path.
+    _check_full(keys, 1001, variant, td.TDES_ENCRYPT, 0x920, offset=8)
+    _check_full(keys, 1000, variant, td.TDES_DECRYPT, 0x921, offset=24)
+    # In place, as the paper's kernel works.
+    _check_full(keys, 4099, variant, td.TDES_ENCRYPT, 0x922, in_place=True)
+    _check_full(keys, 4099, variant, td.TDES_DECRYPT, 0x923, offset=8, in_place=True)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_special_keys_and_data(variant):
+    """Weak keys, all-zero and all-one data (every lane reads the same table entry)."""
+    n = 2500
+    sched_keys = [(bytes.fromhex("0101010101010101"),) * 3,
+                  (bytes.fromhex("fefefefefefefefe"), bytes.fromhex("0101010101010101"), bytes.fromhex("e0e0e0e0f1f1f1f1")),
+                  inputs.key_triple(0x830)]
+    for keys in sched_keys:
+        sched = _gpu.device_sched(*keys)
+        for fill in (0x00, 0xFF):
+            host = np.full(8 * n, fill, np.uint8)
+            src = _gpu.to_device(host)
+            dst = _gpu.empty_like_dev(8 * n)
+            _gpu.run(sched, src, dst, n, td.TDES_ENCRYPT, variant)
+            assert np.array_equal(dst.cpu().numpy(), _gpu.oracle_on_blocks(keys, host, False))
+
+
+def test_variants_agree_and_zero_blocks():
+    keys = inputs.key_triple(0x840)
+    n = 20000
+    host = inputs.message(0x940, n)
+    sched = _gpu.device_sched(*keys)
+    src = _gpu.to_device(host)
+    outs = []
+    for v in VARIANTS:
+        dst = _gpu.empty_like_dev(8 * n)
+        _gpu.run(sched, src, dst, n, td.TDES_ENCRYPT, v)
+        outs.append(dst.cpu().numpy())
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    # n = 0 enqueues nothing and leaves the output untouched.
+    dst = torch.full((64,), 7, dtype=torch.uint8, device=DEV)
+    td.tdes_ecb_encrypt(sched, src, dst, 0)
+    torch.cuda.synchronize()
+    assert bool((dst == 7).all())
+
+
+def test_two_streams_concurrently():
+    keys_a, keys_b = inputs.key_triple(0x850), inputs.key_triple(0x851)
+    n = 300001
+    ha, hb = inputs.message(0x950, n), inputs.message(0x951, n)
+    sa, sb = _gpu.device_sched(*keys_a), _gpu.device_sched(*keys_b)
+    ia, ib = _gpu.to_device(ha), _gpu.to_device(hb)
+    oa, ob = _gpu.empty_like_dev(8 * n), _gpu.empty_like_dev(8 * n)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for _ in range(3):
+        td.tdes_ecb_encrypt(sa, ia, oa, n, stream=s1)
+        td.tdes_ecb_decrypt(sb, ib, ob, n, stream=s2)
+    torch.cuda.synchronize()
+    idx = _gpu.sample_indices(n, 20000, 1)
+    assert np.array_equal(_gpu.gather_blocks(oa, idx), _gpu.oracle_on_blocks(keys_a, inputs.blocks_at(0x950, idx), False))
+    assert np.array_equal(_gpu.gather_blocks(ob, idx), _gpu.oracle_on_blocks(keys_b, inputs.blocks_at(0x951, idx), True))
+
+
+def test_device_generator_matches_host():
+    for seed, n, first in ((1, 1000, 0), (0x3DE50001, 4097, 123456789)):
+        buf = torch.empty(8 * n, dtype=torch.uint8, device=DEV)
+        td.tdes_fill_splitmix64(buf, n, seed, first)
+        torch.cuda.synchronize()
+        assert np.array_equal(buf.cpu().numpy(), inputs.message(seed, n, first_block=first))
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_c2_one_gib_sampled(variant):
+    """The 1 GiB message (2^27 blocks) in the benchmark's configuration: device-resident input,
+    one launch per direction; sampled blocks against the oracle and the full round trip."""
+    n = 1 << 27
+    seed = inputs.DATA_SEED_BASE + 1
+    keys = inputs.key_triple(inputs.KEY_SEED_BASE + 1)
+    sched = _gpu.device_sched(*keys)
+    src = _gpu.device_message(seed, n)
+    ct = torch.empty_like(src)
+    print(f"[parity] C2 1 GiB variant={variant}", flush=True)
+    _gpu.run(sched, src, ct, n, td.TDES_ENCRYPT, variant)
+    idx = _gpu.sample_indices(n, 1 << 15, 2, boundaries=[k << 20 for k in range(1, 128, 7)])
+    host_in = inputs.blocks_at(seed, idx)
+    want = _gpu.oracle_on_blocks(keys, host_in, False)
+    assert np.array_equal(_gpu.gather_blocks(ct, idx), want)
+    pt = torch.empty_like(src)
+    _gpu.run(sched, ct, pt, n, td.TDES_DECRYPT, variant)
+    assert bool(torch.equal(pt, src))
+    del pt, ct, src
+    torch.cuda.empty_cache()

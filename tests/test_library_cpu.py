@@ -1,0 +1,148 @@
+"""Host-side checks of libtdes that need no GPU.
+
+  * the library loads and exports every function include/tdes.h declares;
+  * host key expansion equals the oracle's subkeys, in the order EDE uses them
+    (Section II.A) for both directions;
+  * flags, parity and weak-key rejection, and argument errors are reported
+    before anything reaches a device;
+  * the kernels' compile-time DES constants (des_spec.h) equal the oracle's tables.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1305_4376_amd as td
+from paper_1305_4376_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tdes.h")
+SPEC = os.path.join(ROOT, "paper_1305_4376_amd", "csrc", "des_spec.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(tdes_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_function():
+    lib = td.load_library()
+    names = declared_functions()
+    assert len(names) >= 7
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings():
+    assert td.tdes_status_str(0) == "ok"
+    for code in range(-1, -12, -1):
+        assert td.tdes_status_str(code) != "unknown status"
+    assert td.tdes_status_str(-99) == "unknown status"
+
+
+def _decode(sched: np.ndarray):
+    """The schedule's private round layout, back to 48-bit subkeys (two directions x 48 rounds)."""
+    w = sched.view("<u4")
+    out = []
+    for d in range(2):
+        rounds = []
+        for r in range(48):
+            a, b = int(w[96 * d + 2 * r]), int(w[96 * d + 2 * r + 1])
+            c = [0] * 8
+            c[0], c[6], c[4], c[2] = (a & 63), (a >> 8) & 63, (a >> 16) & 63, (a >> 24) & 63
+            c[1], c[7], c[5], c[3] = (b & 63), (b >> 8) & 63, (b >> 16) & 63, (b >> 24) & 63
+            assert a & 0xC0C0C0C0 == 0 and b & 0xC0C0C0C0 == 0
+            v = 0
+            for x in c:
+                v = (v << 6) | x
+            rounds.append(v)
+        out.append(rounds)
+    return out
+
+
+@pytest.mark.parametrize("keying", [3, 2, 1])
+def test_expand_key_matches_oracle_subkeys(keying):
+    for seed in range(6):
+        k1, k2, k3 = inputs.key_triple(0x700 + seed, keying)
+        enc, dec = _decode(td.tdes_expand_key(k1, k2, k3))
+        s1, s2, s3 = oracle.des_subkeys(k1), oracle.des_subkeys(k2), oracle.des_subkeys(k3)
+        assert enc == s1 + s2[::-1] + s3
+        assert dec == s3[::-1] + s2 + s1[::-1]
+
+
+def test_expand_key_flags():
+    k = inputs.key_triple(0x710)
+    base = td.tdes_expand_key(*k)
+    assert np.array_equal(td.tdes_expand_key(*k, flags=td.TDES_CHECK_PARITY | td.TDES_REJECT_WEAK), base)
+    bad = bytes([k[0][0] ^ 1]) + k[0][1:]
+    # Parity is ignored by default (the standard's PC-1 drops those bits) ...
+    assert np.array_equal(td.tdes_expand_key(bad, k[1], k[2]), base)
+    # ... and rejected on request.
+    with pytest.raises(td.TdesError) as e:
+        td.tdes_expand_key(bad, k[1], k[2], flags=td.TDES_CHECK_PARITY)
+    assert e.value.code == -5
+    for weak in ("0101010101010101", "fefefefefefefefe", "e0e0e0e0f1f1f1f1", "01fe01fe01fe01fe", "1fe01fe00ef10ef1"):
+        w = bytes.fromhex(weak)
+        td.tdes_expand_key(k[0], w, k[2])  # accepted without the flag
+        with pytest.raises(td.TdesError) as e:
+            td.tdes_expand_key(k[0], w, k[2], flags=td.TDES_REJECT_WEAK)
+        assert e.value.code == -6
+    with pytest.raises(td.TdesError) as e:
+        td.tdes_expand_key(*k, flags=8)
+    assert e.value.code == -7
+
+
+def test_expand_key_null_arguments():
+    lib = td.load_library()
+    out = np.zeros(768, np.uint8)
+    k = ctypes.create_string_buffer(b"\x01" * 8, 8)
+    assert lib.tdes_expand_key(None, k, k, 0, out.ctypes.data) == -1
+    assert lib.tdes_expand_key(k, k, k, 0, None) == -1
+
+
+def test_argument_errors_are_host_side():
+    lib = td.load_library()
+    s, a, b = 0x10000, 0x200000, 0x400000
+    # zero blocks: nothing is enqueued, no device is touched
+    assert lib.tdes_ecb_run(s, a, b, 0, 0, 0, None) == 0
+    assert lib.tdes_ecb_encrypt(s, a, a, 0, None) == 0
+    assert lib.tdes_ecb_run(None, a, b, 0, 0, 0, None) == -1
+    assert lib.tdes_ecb_run(s, None, b, 0, 0, 0, None) == -1
+    assert lib.tdes_ecb_run(s, a + 4, b, 0, 0, 0, None) == -2
+    assert lib.tdes_ecb_run(s + 2, a, b, 0, 0, 0, None) == -2
+    assert lib.tdes_ecb_run(s, a, a + 8, 16, 0, 0, None) == -3
+    assert lib.tdes_ecb_run(s, a + 8, a, 16, 0, 0, None) == -3
+    assert lib.tdes_ecb_run(s, a, b, (1 << 58) + 1, 0, 0, None) == -4
+    assert lib.tdes_ecb_run(s, a, b, 0, 2, 0, None) == -7
+    assert lib.tdes_ecb_run(s, a, b, 0, 0, 3, None) == -7
+    assert lib.tdes_sched_upload(None, 0, None, None) == 0
+    assert lib.tdes_sched_upload(None, 1, b, None) == -1
+    assert lib.tdes_fill_splitmix64(None, 0, 1, 0, None) == 0
+    assert lib.tdes_fill_splitmix64(a + 4, 8, 1, 0, None) == -2
+
+
+def _spec_text():
+    return open(SPEC).read()
+
+
+def test_kernel_sboxes_equal_oracle_tables():
+    text = _spec_text()
+    rows = re.findall(r'"([0-9A-F]{16})"', text)
+    assert len(rows) == 32
+    flat = [int(ch, 16) for row in rows for ch in row]
+    assert flat == oracle.table("SBOX")
+
+
+def test_kernel_permutations_equal_oracle_tables():
+    text = _spec_text()
+
+    def arr(name):
+        m = re.search(name + r"\[\d+\]\s*=\s*\{([^}]*)\}", text)
+        return [int(v) + 1 for v in m.group(1).replace("\n", " ").split(",") if v.strip()]
+    assert arr("kP") == oracle.table("P")
+    assert arr("kPC2") == oracle.table("PC2")
+    assert [v - 1 for v in arr("kShift")] == oracle.table("SHIFTS")
