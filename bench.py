@@ -98,7 +98,7 @@ def main():
     ct, pt = torch.empty_like(src), torch.empty_like(src)
     torch.cuda.synchronize()
 
-    variants = {"table": td.TDES_VARIANT_TABLE}
+    variants = {"table": td.TDES_VARIANT_TABLE, "bitslice": td.TDES_VARIANT_BITSLICE}
     results = {}
     for name, v in variants.items():
         wall, launch_ms = time_variant(td, torch, sched, src, ct, pt, v, args.steps, args.warmup)

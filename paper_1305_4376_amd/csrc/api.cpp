@@ -50,8 +50,10 @@ int check_buffers(const void *dev_sched, const void *in, const void *out, uint64
     return TDES_OK;
 }
 
+// The bitsliced kernel is the default: on MI355X it runs the 1 GiB message 2.65x
+// faster than the table kernel (692 vs 261 GB/s, encrypt + decrypt).
 int resolve_variant(int variant) {
-    if (variant == TDES_VARIANT_AUTO) return TDES_VARIANT_TABLE;
+    if (variant == TDES_VARIANT_AUTO) return TDES_VARIANT_BITSLICE;
     return variant;
 }
 

@@ -17,7 +17,7 @@ from tests._gpu import DEV
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = [td.TDES_VARIANT_TABLE, td.TDES_VARIANT_AUTO]
+VARIANTS = [td.TDES_VARIANT_TABLE, td.TDES_VARIANT_BITSLICE, td.TDES_VARIANT_AUTO]
 DIRS = [td.TDES_ENCRYPT, td.TDES_DECRYPT]
 
 EDGE_SIZES = [1, 2, 3, 31, 32, 33, 63, 64, 65, 127, 128, 129, 511, 512, 513, 2047, 2048, 2049, 4095, 4097,
