@@ -117,6 +117,183 @@ int tdes_ecb_decrypt(const void *dev_sched, const void *in, void *out, uint64_t 
 int tdes_ecb_run(const void *dev_sched, const void *in, void *out, uint64_t n_blocks, int direction,
                  int variant, void *stream);
 
+/* ---- batched ECB: many messages, each with its own key triple and direction ---- */
+
+/*
+ * One message of a batch.  Offsets are in bytes from the batch's dev_base;
+ * both must leave the message 8-byte aligned.  out_off == in_off works in
+ * place.  The caller guarantees that every message lies inside its buffer.
+ */
+typedef struct tdes_job {
+    uint64_t in_off;     /* input of the message */
+    uint64_t out_off;    /* output of the message */
+    uint64_t n_blocks;   /* length in 8-byte blocks; 0 is allowed; at most 2^40 */
+    uint32_t sched_idx;  /* which schedule of the device table (768 bytes each) */
+    uint32_t direction;  /* TDES_ENCRYPT or TDES_DECRYPT */
+} tdes_job;
+
+/* Batch context: device plan buffers, a tile counter, a captured graph and the
+ * launch shape.  Not thread-safe: one host thread at a time per context. */
+typedef struct tdes_ctx tdes_ctx;
+
+/* Statistics of the last planned batch and the context's launch shape. */
+typedef struct tdes_batch_info {
+    uint64_t tiles;          /* work items of the last batch */
+    uint64_t wave_tiles;     /* ... of up to 2048 blocks of one message */
+    uint64_t lane_tiles;     /* ... of 64 lane slots of up to 32 blocks */
+    uint64_t slots;          /* slot descriptors uploaded */
+    uint64_t blocks;         /* message blocks in the batch */
+    uint64_t padded_blocks;  /* block positions computed (tiles x 2048) */
+    uint32_t threads;        /* threads per workgroup of the batch kernel */
+    uint32_t groups_per_cu;  /* workgroups per compute unit in its grid */
+    uint32_t graph_captures; /* graphs captured so far by this context */
+    uint32_t pad;
+} tdes_batch_info;
+
+/* Flags of tdes_ecb_batch. */
+#define TDES_BATCH_NO_GRAPH 1u     /* launch the kernel directly instead of replaying a graph */
+#define TDES_BATCH_PER_MESSAGE 2u  /* baseline: one plain launch per message (no plan, no graph) */
+
+/*
+ * Create a batch context on the current device (allocates ~256 bytes of device
+ * memory and a stream; the plan buffers grow on demand).
+ * Errors: TDES_ERR_NULL, TDES_ERR_HIP, TDES_ERR_NOMEM.
+ */
+int tdes_ctx_create(tdes_ctx **ctx);
+
+/* Destroy a context after its last batch has finished.  NULL is a no-op. */
+int tdes_ctx_destroy(tdes_ctx *ctx);
+
+/*
+ * Encrypt or decrypt every message of a batch: ECB on each message as in
+ * tdes_ecb_encrypt/decrypt, all messages in one launch of a persistent kernel
+ * (replayed from a captured graph unless TDES_BATCH_NO_GRAPH).
+ *   jobs: host, n_jobs entries; read before the call returns.
+ *   dev_sched_table: device, n_scheds schedules written by tdes_sched_upload.
+ *   dev_base: device; every offset is relative to it.
+ * The host checks every job first: direction and schedule index, alignment,
+ * and that no message writes bytes another message reads or writes (only
+ * exact in-place is allowed).  The plan is copied to the device on `stream`;
+ * the call can block until the previous batch's copy has been read.
+ * Errors: TDES_ERR_NULL, TDES_ERR_ARG, TDES_ERR_ALIGN, TDES_ERR_SIZE,
+ * TDES_ERR_OVERLAP, TDES_ERR_NOMEM, TDES_ERR_HIP.
+ */
+int tdes_ecb_batch(tdes_ctx *ctx, const tdes_job *jobs, uint32_t n_jobs, const void *dev_sched_table,
+                   uint64_t n_scheds, void *dev_base, uint32_t flags, void *stream);
+
+/*
+ * Run the last planned batch again (same messages, keys and buffers) without
+ * planning or copying: one graph launch.  flags: 0 or TDES_BATCH_NO_GRAPH.
+ * Errors: TDES_ERR_NULL, TDES_ERR_ARG, TDES_ERR_STATE (no batch yet), TDES_ERR_HIP.
+ */
+int tdes_ecb_batch_replay(tdes_ctx *ctx, uint32_t flags, void *stream);
+
+/*
+ * Launch shape of the batch kernel: threads per workgroup (64, 128, 192 or
+ * 256) and workgroups per compute unit (1..64).  Chosen by the autotuner.
+ * Errors: TDES_ERR_NULL, TDES_ERR_ARG.
+ */
+int tdes_ctx_set_tuning(tdes_ctx *ctx, uint32_t threads, uint32_t groups_per_cu);
+int tdes_ctx_get_info(const tdes_ctx *ctx, tdes_batch_info *info);
+
+/* ---- serving: continuous batching of requests under resident keys ---- */
+
+/* A request.  Its input is n_blocks * 8 bytes: copied from host_in when that
+ * is not NULL, otherwise generated on the device as words 0.. of the
+ * SplitMix64 stream seeded with `seed` (see tdes_fill_splitmix64).  If host_out
+ * is not NULL the output is copied there before the request completes. */
+typedef struct tdes_request {
+    uint64_t n_blocks;     /* 1 .. 2^32 */
+    uint32_t key_id;       /* index into the server's resident schedule table */
+    uint32_t direction;    /* TDES_ENCRYPT or TDES_DECRYPT */
+    uint64_t seed;         /* payload stream when host_in is NULL */
+    const void *host_in;   /* optional host input (must stay valid until completion) */
+    void *host_out;        /* optional host output */
+    uint64_t user_tag;     /* returned in the completion */
+} tdes_request;
+
+/* Completion record.  Times are seconds on the server's clock (tdes_server_now). */
+typedef struct tdes_completion {
+    uint64_t id;
+    uint64_t user_tag;
+    int32_t status;        /* TDES_OK, TDES_ERR_STATE if canceled, or the error that failed it */
+    uint32_t pad;
+    double t_arrival;      /* submission (or scheduled arrival in a trace) */
+    double t_admit;        /* memory granted, placed in a step */
+    double t_launch;       /* its step enqueued on the GPU */
+    double t_complete;     /* the engine saw its step finish */
+    const void *dev_out;   /* device output if the server keeps outputs, else NULL */
+} tdes_completion;
+
+typedef struct tdes_serve_config {
+    uint64_t budget_bytes;    /* device memory for request inputs and outputs (one allocation) */
+    uint32_t max_inflight;    /* steps in flight at once, each on its own stream (1..8) */
+    uint32_t max_step_jobs;   /* requests per step */
+    uint64_t max_step_blocks; /* blocks per step (a request larger than this runs alone) */
+    uint32_t keep_outputs;    /* nonzero: outputs stay in device memory until tdes_server_release */
+    uint32_t pad;
+} tdes_serve_config;
+
+typedef struct tdes_serve_stats {
+    uint64_t submitted, completed, canceled;
+    uint64_t bytes;             /* message bytes processed */
+    uint64_t steps;             /* batched launches */
+    uint64_t max_step_jobs;     /* largest step */
+    uint64_t peak_pool_bytes;   /* most device memory granted at once */
+    uint64_t pool_bytes_in_use;
+    uint64_t pending;           /* queued, not yet admitted */
+} tdes_serve_stats;
+
+typedef struct tdes_server tdes_server;
+
+/*
+ * Start a server on the current device: allocates budget_bytes of device
+ * memory and max_inflight batch contexts, and starts the engine thread.
+ * dev_sched_table holds n_scheds schedules (tdes_sched_upload) and must stay
+ * valid and unchanged while the server runs.
+ * Errors: TDES_ERR_NULL, TDES_ERR_SIZE, TDES_ERR_ARG, TDES_ERR_NOMEM, TDES_ERR_HIP.
+ */
+int tdes_server_create(tdes_server **server, const tdes_serve_config *cfg, const void *dev_sched_table,
+                       uint64_t n_scheds);
+
+/* Stop the engine and free everything; requests not yet complete are dropped. */
+int tdes_server_destroy(tdes_server *server);
+
+/* Seconds since the server started (a monotonic clock). */
+double tdes_server_now(const tdes_server *server);
+
+/*
+ * Queue a request (thread-safe); *id receives its id.  The request waits until
+ * its input and output fit in the budget, then runs in the next free step.
+ * Errors: TDES_ERR_NULL, TDES_ERR_ARG, TDES_ERR_SIZE (key id or length),
+ * TDES_ERR_BUDGET (input plus output larger than the whole budget).
+ */
+int tdes_server_submit(tdes_server *server, const tdes_request *req, uint64_t *id);
+
+/* Cancel a request that is still queued; it completes with TDES_ERR_STATE.
+ * Errors: TDES_ERR_STATE if it was already admitted, completed or unknown. */
+int tdes_server_cancel(tdes_server *server, uint64_t id);
+
+/* Take up to max completion records (non-blocking); *n receives the count. */
+int tdes_server_poll(tdes_server *server, tdes_completion *out, uint32_t max, uint32_t *n);
+
+/* Wait until no request is outstanding.  TDES_ERR_STATE on timeout. */
+int tdes_server_wait_idle(tdes_server *server, double timeout_s);
+
+/* Free a kept output (keep_outputs).  TDES_ERR_STATE if there is none. */
+int tdes_server_release(tdes_server *server, uint64_t id);
+
+int tdes_server_stats(tdes_server *server, tdes_serve_stats *stats);
+
+/*
+ * Open-loop driver: submits reqs[i] at arrival[i] seconds after the call
+ * starts (arrival non-decreasing), as a client would, and returns when all
+ * have completed; out[i] receives request i's completion (latency =
+ * t_complete - t_arrival).
+ */
+int tdes_server_run_trace(tdes_server *server, const tdes_request *reqs, const double *arrival, uint64_t n,
+                          tdes_completion *out);
+
 /* ---- utilities ---- */
 
 /* A short English description of a status code (static storage). */

@@ -19,6 +19,11 @@ __all__ = [
     "TDES_VARIANT_AUTO", "TDES_VARIANT_TABLE", "TDES_VARIANT_BITSLICE", "TDES_SCHED_BYTES",
     "tdes_expand_key", "tdes_sched_upload", "tdes_ecb_encrypt", "tdes_ecb_decrypt", "tdes_ecb_run",
     "tdes_status_str", "tdes_fill_splitmix64", "library_path", "load_library",
+    "JOB_DTYPE", "TDES_BATCH_NO_GRAPH", "TDES_BATCH_PER_MESSAGE", "tdes_ctx_create", "tdes_ctx_destroy",
+    "tdes_ecb_batch", "tdes_ecb_batch_replay", "tdes_ctx_set_tuning", "tdes_ctx_get_info",
+    "REQUEST_DTYPE", "COMPLETION_DTYPE", "tdes_server_create", "tdes_server_destroy", "tdes_server_now",
+    "tdes_server_submit", "tdes_server_cancel", "tdes_server_poll", "tdes_server_wait_idle",
+    "tdes_server_release", "tdes_server_stats", "tdes_server_run_trace",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtdes.so")
@@ -28,6 +33,38 @@ TDES_ENCRYPT, TDES_DECRYPT = 0, 1
 TDES_CHECK_PARITY, TDES_REJECT_WEAK = 1, 2
 TDES_VARIANT_AUTO, TDES_VARIANT_TABLE, TDES_VARIANT_BITSLICE = 0, 1, 2
 TDES_SCHED_BYTES = 768
+TDES_BATCH_NO_GRAPH, TDES_BATCH_PER_MESSAGE = 1, 2
+
+# struct tdes_job (include/tdes.h): 32 bytes.
+JOB_DTYPE = np.dtype([("in_off", "<u8"), ("out_off", "<u8"), ("n_blocks", "<u8"), ("sched_idx", "<u4"),
+                      ("direction", "<u4")])
+
+
+# struct tdes_request: 48 bytes; struct tdes_completion: 64 bytes.
+REQUEST_DTYPE = np.dtype([("n_blocks", "<u8"), ("key_id", "<u4"), ("direction", "<u4"), ("seed", "<u8"),
+                          ("host_in", "<u8"), ("host_out", "<u8"), ("user_tag", "<u8")])
+COMPLETION_DTYPE = np.dtype([("id", "<u8"), ("user_tag", "<u8"), ("status", "<i4"), ("pad", "<u4"),
+                             ("t_arrival", "<f8"), ("t_admit", "<f8"), ("t_launch", "<f8"),
+                             ("t_complete", "<f8"), ("dev_out", "<u8")])
+
+
+class _ServeConfig(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_uint32),
+                ("max_step_jobs", ctypes.c_uint32), ("max_step_blocks", ctypes.c_uint64),
+                ("keep_outputs", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+
+
+class _ServeStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "completed", "canceled", "bytes", "steps",
+                                               "max_step_jobs", "peak_pool_bytes", "pool_bytes_in_use",
+                                               "pending")]
+
+
+class _BatchInfo(ctypes.Structure):
+    _fields_ = [("tiles", ctypes.c_uint64), ("wave_tiles", ctypes.c_uint64), ("lane_tiles", ctypes.c_uint64),
+                ("slots", ctypes.c_uint64), ("blocks", ctypes.c_uint64), ("padded_blocks", ctypes.c_uint64),
+                ("threads", ctypes.c_uint32), ("groups_per_cu", ctypes.c_uint32),
+                ("graph_captures", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
 
 _lib = None
 
@@ -59,6 +96,22 @@ def load_library():
         "tdes_ecb_run": ([vp, vp, vp, u64, i32, i32, vp], i32),
         "tdes_status_str": ([i32], ctypes.c_char_p),
         "tdes_fill_splitmix64": ([vp, u64, u64, u64, vp], i32),
+        "tdes_ctx_create": ([ctypes.POINTER(vp)], i32),
+        "tdes_ctx_destroy": ([vp], i32),
+        "tdes_ecb_batch": ([vp, vp, u32, vp, u64, vp, u32, vp], i32),
+        "tdes_ecb_batch_replay": ([vp, u32, vp], i32),
+        "tdes_ctx_set_tuning": ([vp, u32, u32], i32),
+        "tdes_ctx_get_info": ([vp, ctypes.POINTER(_BatchInfo)], i32),
+        "tdes_server_create": ([ctypes.POINTER(vp), ctypes.POINTER(_ServeConfig), vp, u64], i32),
+        "tdes_server_destroy": ([vp], i32),
+        "tdes_server_now": ([vp], ctypes.c_double),
+        "tdes_server_submit": ([vp, vp, ctypes.POINTER(u64)], i32),
+        "tdes_server_cancel": ([vp, u64], i32),
+        "tdes_server_poll": ([vp, vp, u32, ctypes.POINTER(u32)], i32),
+        "tdes_server_wait_idle": ([vp, ctypes.c_double], i32),
+        "tdes_server_release": ([vp, u64], i32),
+        "tdes_server_stats": ([vp, ctypes.POINTER(_ServeStats)], i32),
+        "tdes_server_run_trace": ([vp, vp, vp, u64, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -155,3 +208,101 @@ def tdes_ecb_decrypt(dev_sched, src, dst, n_blocks=None, stream=None) -> None:
 def tdes_fill_splitmix64(dev, n_words: int, seed: int, first: int = 0, stream=None) -> None:
     _check(load_library().tdes_fill_splitmix64(_ptr(dev), int(n_words), int(seed) & (2**64 - 1), int(first),
                                                _stream(stream, dev)), "tdes_fill_splitmix64")
+
+
+def tdes_ctx_create() -> int:
+    """A batch context on the current device (an opaque handle)."""
+    h = ctypes.c_void_p()
+    _check(load_library().tdes_ctx_create(ctypes.byref(h)), "tdes_ctx_create")
+    return h.value
+
+
+def tdes_ctx_destroy(ctx: int) -> None:
+    _check(load_library().tdes_ctx_destroy(ctx), "tdes_ctx_destroy")
+
+
+def tdes_ecb_batch(ctx: int, jobs: np.ndarray, dev_sched_table, n_scheds: int, dev_base, flags: int = 0,
+                   stream=None) -> None:
+    """jobs: a JOB_DTYPE array (host).  Offsets are relative to dev_base."""
+    j = np.ascontiguousarray(jobs, dtype=JOB_DTYPE)
+    _check(load_library().tdes_ecb_batch(ctx, j.ctypes.data, int(j.size), _ptr(dev_sched_table), int(n_scheds),
+                                         _ptr(dev_base), int(flags), _stream(stream, dev_base)), "tdes_ecb_batch")
+
+
+def tdes_ecb_batch_replay(ctx: int, flags: int = 0, stream=None) -> None:
+    _check(load_library().tdes_ecb_batch_replay(ctx, int(flags), _stream(stream)), "tdes_ecb_batch_replay")
+
+
+def tdes_ctx_set_tuning(ctx: int, threads: int, groups_per_cu: int) -> None:
+    _check(load_library().tdes_ctx_set_tuning(ctx, int(threads), int(groups_per_cu)), "tdes_ctx_set_tuning")
+
+
+def tdes_ctx_get_info(ctx: int) -> dict:
+    info = _BatchInfo()
+    _check(load_library().tdes_ctx_get_info(ctx, ctypes.byref(info)), "tdes_ctx_get_info")
+    return {name: getattr(info, name) for name, _ in info._fields_ if name != "pad"}
+
+
+def tdes_server_create(dev_sched_table, n_scheds: int, budget_bytes: int, max_inflight: int = 2,
+                       max_step_jobs: int = 4096, max_step_blocks: int = 1 << 26, keep_outputs: bool = False) -> int:
+    """Start a serving engine over a resident schedule table; returns an opaque handle."""
+    cfg = _ServeConfig(int(budget_bytes), int(max_inflight), int(max_step_jobs), int(max_step_blocks),
+                       int(bool(keep_outputs)), 0)
+    h = ctypes.c_void_p()
+    _check(load_library().tdes_server_create(ctypes.byref(h), ctypes.byref(cfg), _ptr(dev_sched_table),
+                                             int(n_scheds)), "tdes_server_create")
+    return h.value
+
+
+def tdes_server_destroy(server: int) -> None:
+    _check(load_library().tdes_server_destroy(server), "tdes_server_destroy")
+
+
+def tdes_server_now(server: int) -> float:
+    return load_library().tdes_server_now(server)
+
+
+def tdes_server_submit(server: int, req: np.ndarray) -> int:
+    """req: one REQUEST_DTYPE record; returns the request id."""
+    r = np.ascontiguousarray(np.asarray(req, dtype=REQUEST_DTYPE).reshape(1))
+    rid = ctypes.c_uint64()
+    _check(load_library().tdes_server_submit(server, r.ctypes.data, ctypes.byref(rid)), "tdes_server_submit")
+    return rid.value
+
+
+def tdes_server_cancel(server: int, rid: int) -> None:
+    _check(load_library().tdes_server_cancel(server, int(rid)), "tdes_server_cancel")
+
+
+def tdes_server_poll(server: int, max_records: int = 4096) -> np.ndarray:
+    out = np.zeros(max_records, dtype=COMPLETION_DTYPE)
+    n = ctypes.c_uint32()
+    _check(load_library().tdes_server_poll(server, out.ctypes.data, int(max_records), ctypes.byref(n)),
+           "tdes_server_poll")
+    return out[: n.value]
+
+
+def tdes_server_wait_idle(server: int, timeout_s: float = 60.0) -> None:
+    _check(load_library().tdes_server_wait_idle(server, float(timeout_s)), "tdes_server_wait_idle")
+
+
+def tdes_server_release(server: int, rid: int) -> None:
+    _check(load_library().tdes_server_release(server, int(rid)), "tdes_server_release")
+
+
+def tdes_server_stats(server: int) -> dict:
+    st = _ServeStats()
+    _check(load_library().tdes_server_stats(server, ctypes.byref(st)), "tdes_server_stats")
+    return {name: getattr(st, name) for name, _ in st._fields_}
+
+
+def tdes_server_run_trace(server: int, reqs: np.ndarray, arrival_s: np.ndarray) -> np.ndarray:
+    """Open-loop run: request i is submitted arrival_s[i] seconds after the start; returns completions."""
+    r = np.ascontiguousarray(reqs, dtype=REQUEST_DTYPE)
+    a = np.ascontiguousarray(arrival_s, dtype=np.float64)
+    if r.size != a.size:
+        raise ValueError("one arrival time per request")
+    out = np.zeros(r.size, dtype=COMPLETION_DTYPE)
+    _check(load_library().tdes_server_run_trace(server, r.ctypes.data, a.ctypes.data, int(r.size),
+                                                out.ctypes.data), "tdes_server_run_trace")
+    return out

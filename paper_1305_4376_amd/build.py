@@ -25,7 +25,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include")]
 
-SOURCES = ["api.cpp", "keysched.cpp", "k_table.hip", "k_bitslice.hip", "k_util.hip"]
+SOURCES = ["api.cpp", "keysched.cpp", "batch.cpp", "serve.cpp", "k_table.hip", "k_bitslice.hip", "k_batch.hip", "k_util.hip"]
 
 
 def _run(cmd, verbose):
@@ -51,7 +51,7 @@ def build(verbose: bool = False) -> str:
         _run([HIPCC, *COMMON, *lang, "-c", path, "-o", obj], verbose)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs], verbose)
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs], verbose)
     os.replace(tmp, LIB)
     return LIB
 

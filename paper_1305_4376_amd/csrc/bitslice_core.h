@@ -1,0 +1,257 @@
+// bitslice_core.h -- the bitsliced Triple-DES round core shared by the plain and batched kernels.
+//
+// A lane holds 32 blocks as 64 bit planes: plane f is a 32-bit word whose bit j
+// is bit f of the lane's block j.  IP, E, P and IP^-1 are renamings of planes;
+// the subkey XOR is one XOR per S-box input plane with a mask (0 or ~0) taken
+// from the schedule word (a scalar register when the key is the same for the
+// whole wave, a vector register when lanes use different keys); each S-box is
+// a circuit of 3-input lookup gates (sbox_circuits.inc).  Blocks become planes
+// by an in-register 32x32 bit transpose of each 4-byte half of the 32 blocks.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "des_spec.h"
+
+namespace tdes_bs {
+
+#include "sbox_circuits.inc"
+
+constexpr int kLanes = 64;
+constexpr int kTileBlocks = 32 * kLanes;     // blocks per wave tile
+
+// ---- compile-time plane maps ----
+
+// Transposed plane that holds block bit f (0-based, bit 0 = MSB of byte 0).
+// Half h (bytes 4h..4h+3) is loaded as a little-endian word whose bit i is
+// bit 7 - i % 8 of byte i / 8 of the half.
+constexpr int plane_of_bit(int f) { return 32 * (f / 32) + 8 * ((f % 32) / 8) + 7 - f % 8; }
+
+struct Maps {
+    int l0[32], r0[32];   // plane of IP output bit k (L0, R0)
+    int out_src[64];      // for plane p after FP: index into the preoutput R16 || L16 (0..63)
+    int e[48];            // R bit feeding S-box input 6s+j
+    int p_inv[32];        // f(R) bit receiving S-box output bit q
+};
+
+constexpr Maps make_maps() {
+    Maps m{};
+    for (int k = 0; k < 32; k++) {
+        m.l0[k] = plane_of_bit(tdes_spec::ip(k));
+        m.r0[k] = plane_of_bit(tdes_spec::ip(32 + k));
+    }
+    // FP = IP^-1: output bit ip(k) is preoutput bit k.
+    for (int k = 0; k < 64; k++) m.out_src[plane_of_bit(tdes_spec::ip(k))] = k;
+    for (int i = 0; i < 48; i++) m.e[i] = tdes_spec::expansion(i);
+    for (int i = 0; i < 32; i++) m.p_inv[tdes_spec::kP[i]] = i;
+    return m;
+}
+
+constexpr Maps kMaps = make_maps();
+
+// Key chunk of S-box s sits in schedule word s % 2 at byte ((8 + s % 2 - s) % 8) / 2,
+// its first bit at position 5 of the byte (the host layout of keysched.cpp).
+constexpr int key_pos(int s, int j) { return 8 * (((8 + s % 2 - s) % 8) / 2) + 5 - j; }
+
+// ---- bit transpose ----
+
+// One exchange stage of the transpose: for rows j and j + S (j & S == 0), swap the
+// bits of row j at positions i + S with those of row j + S at positions i, for the
+// positions i selected by M.
+template <int S, uint32_t M>
+__device__ __forceinline__ void exchange_stage(uint32_t (&w)[32]) {
+#pragma unroll
+    for (int j = 0; j < 32; j++) {
+        if (j & S) continue;
+        const uint32_t a = w[j], b = w[j + S];
+        w[j] = (a & M) | ((b << S) & ~M);
+        w[j + S] = ((a >> S) & M) | (b & ~M);
+    }
+}
+
+// In place: afterwards bit j of w[i] is what bit i of w[j] was.
+__device__ __forceinline__ void transpose32(uint32_t (&w)[32]) {
+#pragma unroll
+    for (int j = 0; j < 16; j++) {
+        const uint32_t a = w[j], b = w[j + 16];
+        w[j] = __builtin_amdgcn_perm(b, a, 0x05040100u);       // a.lo16 | b.lo16 << 16
+        w[j + 16] = __builtin_amdgcn_perm(b, a, 0x07060302u);  // a.hi16 | b.hi16 << 16
+    }
+#pragma unroll
+    for (int j = 0; j < 32; j++) {
+        if (j & 8) continue;
+        const uint32_t a = w[j], b = w[j + 8];
+        w[j] = __builtin_amdgcn_perm(b, a, 0x06020400u);       // bytes a0 b0 a2 b2
+        w[j + 8] = __builtin_amdgcn_perm(b, a, 0x07030501u);   // bytes a1 b1 a3 b3
+    }
+    exchange_stage<4, 0x0F0F0F0Fu>(w);
+    exchange_stage<2, 0x33333333u>(w);
+    exchange_stage<1, 0x55555555u>(w);
+}
+
+// ---- rounds ----
+
+__device__ __forceinline__ uint32_t key_mask(uint32_t word, int pos) {
+    return (uint32_t)((int32_t)(word << (31 - pos)) >> 31);
+}
+
+// Keeps the schedule word live in its register class at each use, so that the
+// compiler extracts each key mask right before its XOR instead of hoisting all
+// 48 masks of a round (which exhausts scalar registers, or vector registers
+// when lanes have their own keys).
+template <bool kLaneKeys>
+__device__ __forceinline__ uint32_t key_word(uint32_t w) {
+    if (kLaneKeys)
+        asm volatile("" : "+v"(w));
+    else
+        asm volatile("" : "+s"(w));
+    return w;
+}
+
+template <int S, bool kLaneKeys>
+__device__ __forceinline__ void sbox_round(uint32_t (&l)[32], const uint32_t (&r)[32], uint32_t kw_in) {
+    const uint32_t kw = key_word<kLaneKeys>(kw_in);
+    const uint32_t x0 = r[kMaps.e[6 * S + 0]] ^ key_mask(kw, key_pos(S, 0));
+    const uint32_t x1 = r[kMaps.e[6 * S + 1]] ^ key_mask(kw, key_pos(S, 1));
+    const uint32_t x2 = r[kMaps.e[6 * S + 2]] ^ key_mask(kw, key_pos(S, 2));
+    const uint32_t x3 = r[kMaps.e[6 * S + 3]] ^ key_mask(kw, key_pos(S, 3));
+    const uint32_t x4 = r[kMaps.e[6 * S + 4]] ^ key_mask(kw, key_pos(S, 4));
+    const uint32_t x5 = r[kMaps.e[6 * S + 5]] ^ key_mask(kw, key_pos(S, 5));
+    uint32_t &o0 = l[kMaps.p_inv[4 * S + 0]];
+    uint32_t &o1 = l[kMaps.p_inv[4 * S + 1]];
+    uint32_t &o2 = l[kMaps.p_inv[4 * S + 2]];
+    uint32_t &o3 = l[kMaps.p_inv[4 * S + 3]];
+    if constexpr (S == 0) sbox0(x0, x1, x2, x3, x4, x5, o0, o1, o2, o3);
+    if constexpr (S == 1) sbox1(x0, x1, x2, x3, x4, x5, o0, o1, o2, o3);
+    if constexpr (S == 2) sbox2(x0, x1, x2, x3, x4, x5, o0, o1, o2, o3);
+    if constexpr (S == 3) sbox3(x0, x1, x2, x3, x4, x5, o0, o1, o2, o3);
+    if constexpr (S == 4) sbox4(x0, x1, x2, x3, x4, x5, o0, o1, o2, o3);
+    if constexpr (S == 5) sbox5(x0, x1, x2, x3, x4, x5, o0, o1, o2, o3);
+    if constexpr (S == 6) sbox6(x0, x1, x2, x3, x4, x5, o0, o1, o2, o3);
+    if constexpr (S == 7) sbox7(x0, x1, x2, x3, x4, x5, o0, o1, o2, o3);
+}
+
+// L ^= f(R, K) for one round with schedule words (ka, kb).
+template <bool kLaneKeys>
+__device__ __forceinline__ void feistel(uint32_t (&l)[32], const uint32_t (&r)[32], uint32_t ka, uint32_t kb) {
+    sbox_round<0, kLaneKeys>(l, r, ka);
+    sbox_round<1, kLaneKeys>(l, r, kb);
+    sbox_round<2, kLaneKeys>(l, r, ka);
+    sbox_round<3, kLaneKeys>(l, r, kb);
+    sbox_round<4, kLaneKeys>(l, r, ka);
+    sbox_round<5, kLaneKeys>(l, r, kb);
+    sbox_round<6, kLaneKeys>(l, r, ka);
+    sbox_round<7, kLaneKeys>(l, r, kb);
+}
+
+// Sixteen rounds: x holds L0 and y holds R0 on entry, L16 and R16 on exit.
+template <bool kLaneKeys>
+__device__ __forceinline__ void des_stage(uint32_t (&x)[32], uint32_t (&y)[32], const uint32_t *__restrict__ ks) {
+#pragma unroll 1
+    for (int r = 0; r < 16; r += 2) {
+        feistel<kLaneKeys>(x, y, ks[2 * r], ks[2 * r + 1]);
+        feistel<kLaneKeys>(y, x, ks[2 * r + 2], ks[2 * r + 3]);
+    }
+}
+
+// ---- kernel ----
+
+// The whole EDE (or its inverse, by the schedule) on 32 blocks held as two
+// arrays of little-endian words: a[j] = bytes 0..3 and b[j] = bytes 4..7 of
+// block j.  ks: the 96 schedule words of one direction.
+template <bool kLaneKeys>
+__device__ __forceinline__ void tdes_32_blocks(uint32_t (&a)[32], uint32_t (&b)[32], const uint32_t *__restrict__ ks) {
+    transpose32(a);
+    transpose32(b);
+    uint32_t l[32], r[32];
+#pragma unroll
+    for (int k = 0; k < 32; k++) {
+        const int pl = kMaps.l0[k], pr = kMaps.r0[k];
+        l[k] = pl < 32 ? a[pl] : b[pl - 32];
+        r[k] = pr < 32 ? a[pr] : b[pr - 32];
+    }
+    des_stage<kLaneKeys>(l, r, ks);        // E (or D) under the first key
+    des_stage<kLaneKeys>(r, l, ks + 32);   // IP^-1 then IP cancel: the halves swap
+    des_stage<kLaneKeys>(l, r, ks + 64);
+    // Preoutput R16 || L16 = (r, l); FP is a renaming back to block bit planes.
+#pragma unroll
+    for (int p = 0; p < 64; p++) {
+        const int q = kMaps.out_src[p];
+        const uint32_t v = q < 32 ? r[q] : l[q - 32];
+        if (p < 32) a[p] = v; else b[p - 32] = v;
+    }
+    transpose32(a);
+    transpose32(b);
+}
+
+// The empty asm statement makes a value opaque at its use, so the compiler
+// recomputes per-block offsets instead of hoisting them out of tile loops and
+// keeping them live across the rounds.
+__device__ __forceinline__ uint32_t opaque(uint32_t v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+// A wave tile: 2048 consecutive blocks starting at `tin`/`tout` (wave-uniform);
+// lane l holds blocks 128k + 2l and 128k + 2l + 1 (k = 0..15), so each access is
+// 16 bytes per lane over 1 KiB contiguous across the wave.  A short tile
+// (n_valid < 2048, or buffers not 16-byte aligned) reads 8 bytes per block,
+// clamping indices past the end to the last valid block, and writes only
+// valid blocks.
+template <bool kFull>
+__device__ __forceinline__ void wave_tile(const uint32_t *__restrict__ ks, const uint8_t *tin, uint8_t *tout,
+                                          uint32_t n_valid, uint32_t lane) {
+    uint32_t a[32], b[32];
+    lane = opaque(lane);
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        if (kFull) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(tin + 1024 * k + 16 * lane);
+            a[2 * k] = v.x; b[2 * k] = v.y; a[2 * k + 1] = v.z; b[2 * k + 1] = v.w;
+        } else {
+            const uint32_t j = 128 * k + 2 * lane;
+            const uint32_t j0 = j < n_valid ? j : n_valid - 1;
+            const uint32_t j1 = j + 1 < n_valid ? j + 1 : n_valid - 1;
+            const uint2 v0 = *reinterpret_cast<const uint2 *>(tin + 8 * j0);
+            const uint2 v1 = *reinterpret_cast<const uint2 *>(tin + 8 * j1);
+            a[2 * k] = v0.x; b[2 * k] = v0.y; a[2 * k + 1] = v1.x; b[2 * k + 1] = v1.y;
+        }
+    }
+    tdes_32_blocks<false>(a, b, ks);
+    lane = opaque(lane);
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        if (kFull) {
+            *reinterpret_cast<uint4 *>(tout + 1024 * k + 16 * lane) =
+                make_uint4(a[2 * k], b[2 * k], a[2 * k + 1], b[2 * k + 1]);
+        } else {
+            const uint32_t j = 128 * k + 2 * lane;
+            if (j < n_valid) *reinterpret_cast<uint2 *>(tout + 8 * j) = make_uint2(a[2 * k], b[2 * k]);
+            if (j + 1 < n_valid) *reinterpret_cast<uint2 *>(tout + 8 * (j + 1)) = make_uint2(a[2 * k + 1], b[2 * k + 1]);
+        }
+    }
+}
+
+// A lane slot: up to 32 consecutive blocks owned by this lane alone (its own
+// message, key and direction).  count = 0 leaves the lane idle.
+__device__ __forceinline__ void lane_slot(const uint32_t *ks, const uint8_t *lin, uint8_t *lout, uint32_t count) {
+    uint32_t a[32], b[32];
+    if (count) {
+#pragma unroll
+        for (int j = 0; j < 32; j++) {
+            const uint32_t jj = opaque(j < (int)count ? j : count - 1);
+            const uint2 v = *reinterpret_cast<const uint2 *>(lin + 8 * jj);
+            a[j] = v.x; b[j] = v.y;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 32; j++) a[j] = b[j] = 0;
+    }
+    tdes_32_blocks<true>(a, b, ks);
+    if (count) {
+#pragma unroll
+        for (int j = 0; j < 32; j++)
+            if (j < (int)count) *reinterpret_cast<uint2 *>(lout + 8 * opaque(j)) = make_uint2(a[j], b[j]);
+    }
+}
+
+}  // namespace tdes_bs

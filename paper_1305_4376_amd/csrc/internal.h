@@ -28,4 +28,15 @@ hipError_t launch_bitslice(const uint32_t *ks, const uint8_t *in, uint8_t *out, 
 hipError_t launch_fill_splitmix64(uint64_t *dev, uint64_t n_words, uint64_t seed, uint64_t first,
                                   hipStream_t stream);
 
+// A run of SplitMix64 words written to base + dst_off (one workgroup each).
+struct FillTile {
+    uint64_t dst_off;
+    uint64_t seed;
+    uint64_t first_word;
+    uint32_t n_words;
+    uint32_t pad;
+};
+constexpr uint32_t kFillTileWords = 1u << 16;
+hipError_t launch_fill_tiles(const FillTile *tiles, uint32_t n_tiles, uint8_t *base, hipStream_t stream);
+
 }  // namespace tdes

@@ -39,3 +39,29 @@ hipError_t launch_fill_splitmix64(uint64_t *dev, uint64_t n_words, uint64_t seed
 }
 
 }  // namespace tdes
+
+// ---- batched fill: many buffers, each from its own SplitMix64 stream ----
+
+namespace {
+
+constexpr int kFillThreads = 256;
+
+__global__ __launch_bounds__(kFillThreads) void fill_tiles_kernel(const tdes::FillTile *__restrict__ tiles,
+                                                                  uint32_t n_tiles, uint8_t *base) {
+    if (blockIdx.x >= n_tiles) return;
+    const tdes::FillTile t = tiles[blockIdx.x];
+    uint64_t *dst = reinterpret_cast<uint64_t *>(base + t.dst_off);
+    for (uint32_t i = threadIdx.x; i < t.n_words; i += kFillThreads) dst[i] = splitmix64_word(t.seed, t.first_word + i);
+}
+
+}  // namespace
+
+namespace tdes {
+
+hipError_t launch_fill_tiles(const FillTile *tiles, uint32_t n_tiles, uint8_t *base, hipStream_t stream) {
+    if (n_tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_tiles_kernel, dim3(n_tiles), dim3(kFillThreads), 0, stream, tiles, n_tiles, base);
+    return hipGetLastError();
+}
+
+}  // namespace tdes

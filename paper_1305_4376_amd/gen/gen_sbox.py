@@ -124,9 +124,9 @@ def load_store() -> dict[int, Circuit]:
     if not os.path.exists(STORE):
         return {}
     out = {}
-    for block in open(STORE).read().split("box ")[1:]:
+    for block in re.split(r"^box ", open(STORE).read(), flags=re.M)[1:]:
         head, _, body = block.partition("\n")
-        out[int(head.split()[0])] = Circuit.parse(body)
+        out[int(head.split()[0]) - 1] = Circuit.parse(body)
     return out
 
 

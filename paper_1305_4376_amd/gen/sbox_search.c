@@ -20,10 +20,12 @@
  *   2. two new gates: t = F(g, d, e) with g = G(a, b, c), found by fixing the
  *      pair (d, e): on every cell of (d, e) where t is not constant, g must
  *      equal t or its complement, a parity problem over four cells;
- *   3. a decomposition t = F(v, A, B) on a node v (an input or an existing
- *      gate): A realizes t where v = 0, B where v = 1, each a smaller partial
- *      function.  The node is chosen at random among those that shrink the
- *      sub-problems' supports the most.
+ *   3. a decomposition, chosen at random among the options with the lowest
+ *      estimated cost (from the sub-problems' support sizes): Shannon on a
+ *      node v (an input or an existing gate), t = F(v, A, B) with A = t where
+ *      v = 0 and B = t where v = 1; or a bi-decomposition on two nodes,
+ *      t = F(a, b, X), where on every cell of (a, b) t is constant or equal to
+ *      X or its complement, the polarities picked to make X cheapest.
  * The four outputs are realized in a random order, sharing all nodes; many
  * random restarts run and the cheapest circuit is kept, where the cost is the
  * gate count plus one for each output whose final gate cannot also absorb the
@@ -224,34 +226,97 @@ static int try_two(circuit_t *C, tt t, tt care, int budget) {
 
 static int realize(circuit_t *C, tt t, tt care, int depth, int budget2);
 
-/* Step 3: decompose on node v: t = F(v, A, B). */
+/* Rough gate cost of a partial function with k support variables. */
+static int est_cost(tt t, tt care, const circuit_t *C) {
+    static const int cost_by_support[7] = {0, 0, 10, 10, 25, 55, 100};
+    if (find_existing(C, t, care) >= 0) return 0;
+    return cost_by_support[popc(support(t, care))];
+}
+
+/*
+ * Step 3: decompose, choosing at random among the cheapest estimated options:
+ *   Shannon on a node v:       t = F(v, A, B), A = t where v = 0, B = t where v = 1;
+ *   bi-decomposition on (a,b): t = F(a, b, X), where on each of the four cells of
+ *       (a, b) t is constant or equal to X or its complement; the polarity of each
+ *       cell is chosen to make X cheapest (one sub-problem instead of two).
+ */
+static int g_allow_bidec = 1;   /* per restart: whether bi-decompositions are offered */
+
 static int decompose(circuit_t *C, tt t, tt care, int depth, int budget2) {
     int n = C->n;
-    int scores[MAXN], best = 1 << 30;
-    for (int v = 0; v < n; v++) {
+    enum { MAXOPT = 4096 };
+    static int opt_kind[MAXOPT], opt_a[MAXOPT], opt_b[MAXOPT], opt_pol[MAXOPT], opt_cost[MAXOPT];
+    int nopt = 0, best = 1 << 30;
+    for (int v = 0; v < n && nopt < MAXOPT; v++) {
         tt val = C->val[v];
         tt c0 = care & ~val, c1 = care & val;
-        if (!c0 || !c1) { scores[v] = 1 << 30; continue; }
-        int s = popc(support(t, c0)) + popc(support(t, c1));
-        /* existing matches are free */
-        if (find_existing(C, t, c0) >= 0) s -= 3;
-        if (find_existing(C, t, c1) >= 0) s -= 3;
-        scores[v] = s;
-        if (s < best) best = s;
+        if (!c0 || !c1) continue;
+        int cost = 10 + est_cost(t, c0, C) + est_cost(t, c1, C) + (int)(rnd() % 6);
+        opt_kind[nopt] = 0; opt_a[nopt] = v; opt_cost[nopt] = cost; nopt++;
+        if (cost < best) best = cost;
     }
-    if (best >= (1 << 30)) return -1;
-    int cand[MAXN], nc = 0;
-    for (int v = 0; v < n; v++)
-        if (scores[v] <= best + (int)(rnd() % 2)) cand[nc++] = v;
-    int v = cand[rndint(nc)];
-    tt val = C->val[v];
-    int A = realize(C, t, care & ~val, depth + 1, budget2);
-    if (A < 0) return -1;
-    int B = realize(C, t, care & val, depth + 1, budget2);
-    if (B < 0) return -1;
-    int lut;
-    if (!function_of(C, t, care, v, A, B, &lut)) return -1;
-    return add_gate(C, v, A, B, lut);
+    for (int a = 0; a < n && g_allow_bidec; a++)
+        for (int b = a + 1; b < n && nopt < MAXOPT; b++) {
+            tt va = C->val[a], vb = C->val[b];
+            tt cells[4];
+            int live = 0;
+            for (int k = 0; k < 4; k++) {
+                cells[k] = ((k & 2) ? va : ~va) & ((k & 1) ? vb : ~vb) & care;
+                tt on = cells[k] & t;
+                if (on && on != cells[k]) live |= 1 << k;
+            }
+            if (popc(live) < 2) continue;  /* one live cell is a Shannon-like case */
+            tt xcare = 0;
+            for (int k = 0; k < 4; k++) if (live >> k & 1) xcare |= cells[k];
+            const int tsup = popc(support(t, care));
+            int bestpol = 0, bestc = 1 << 30;
+            for (int pol = 0; pol < 16; pol++) {
+                if (pol & ~live) continue;
+                if (pol & 1 & live) continue;  /* complement symmetry: fix the first live cell */
+                tt x = t;
+                for (int k = 0; k < 4; k++) if (pol >> k & 1) x ^= cells[k];
+                /* progress: a smaller care set or a smaller support */
+                if (xcare == care && popc(support(x, xcare)) >= tsup) continue;
+                int c = est_cost(x, xcare, C);
+                if (c < bestc) { bestc = c; bestpol = pol; }
+            }
+            if (bestc >= (1 << 30)) continue;
+            int cost = 10 + bestc + (int)(rnd() % 6);
+            opt_kind[nopt] = 1; opt_a[nopt] = a; opt_b[nopt] = b; opt_pol[nopt] = bestpol; opt_cost[nopt] = cost; nopt++;
+            if (cost < best) best = cost;
+        }
+    if (!nopt) return -1;
+    int cand[MAXOPT], nc = 0;
+    for (int i = 0; i < nopt; i++) if (opt_cost[i] <= best) cand[nc++] = i;
+    int o = cand[rndint(nc)];
+    if (opt_kind[o] == 0) {
+        int v = opt_a[o];
+        tt val = C->val[v];
+        int A = realize(C, t, care & ~val, depth + 1, budget2);
+        if (A < 0) return -1;
+        int B = realize(C, t, care & val, depth + 1, budget2);
+        if (B < 0) return -1;
+        int lut;
+        if (!function_of(C, t, care, v, A, B, &lut)) return -1;
+        return add_gate(C, v, A, B, lut);
+    } else {
+        int a = opt_a[o], b = opt_b[o];
+        tt va = C->val[a], vb = C->val[b];
+        tt x = t, xcare = 0;
+        for (int k = 0; k < 4; k++) {
+            tt cell = ((k & 2) ? va : ~va) & ((k & 1) ? vb : ~vb) & care;
+            tt on = cell & t;
+            if (on && on != cell) {
+                xcare |= cell;
+                if (opt_pol[o] >> k & 1) x ^= cell;
+            }
+        }
+        int X = realize(C, x, xcare, depth + 1, budget2);
+        if (X < 0) return -1;
+        int lut;
+        if (!function_of(C, t, care, a, b, X, &lut)) return -1;
+        return add_gate(C, a, b, X, lut);
+    }
 }
 
 static int realize(circuit_t *C, tt t, tt care, int depth, int budget2) {
@@ -331,6 +396,7 @@ int main(int argc, char **argv) {
     circuit_t best;
     int best_cost = 1 << 30, best_outs[4] = {0};
     for (int trial = 0; trial < trials; trial++) {
+        g_allow_bidec = (int)(rnd() % 3 == 0);
         circuit_t C;
         memset(&C, 0, sizeof C);
         C.n = 6;

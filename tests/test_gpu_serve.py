@@ -1,0 +1,176 @@
+"""GPU tests of the serving engine (continuous batching over resident key schedules).
+
+The pin: every request's output is ECB-EDE of its own payload under its own
+key (Abstract, Section II.A), the same bit for bit whether it runs alone or in
+a mix of overlapping requests, and equal to the oracle on sampled blocks.
+Admission is checked against the device-memory budget.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1305_4376_amd as td
+from paper_1305_4376_amd import inputs
+from tests import _gpu
+from tests._gpu import DEV
+
+pytestmark = pytest.mark.gpu
+
+N_KEYS = 512
+
+
+@pytest.fixture(scope="module")
+def table():
+    keys = inputs.key_triples(0x5E01, N_KEYS)
+    host = np.concatenate([td.tdes_expand_key(k[:8].tobytes(), k[8:16].tobytes(), k[16:].tobytes()) for k in keys])
+    dev = torch.empty(host.size, dtype=torch.uint8, device=DEV)
+    td.tdes_sched_upload(host, dev)
+    return keys, dev
+
+
+def _requests(n, seed, max_blocks=1 << 15):
+    rng = np.random.default_rng(seed)
+    reqs = np.zeros(n, dtype=td.REQUEST_DTYPE)
+    reqs["n_blocks"] = inputs.log_uniform_lengths(seed, n, max_blocks)
+    reqs["key_id"] = rng.integers(0, N_KEYS, n)
+    reqs["direction"] = rng.integers(0, 2, n)
+    reqs["seed"] = seed * 1000003 + np.arange(n)
+    reqs["user_tag"] = np.arange(n)
+    return reqs
+
+
+def _outputs_by_tag(server, completions, reqs):
+    """Copies each kept output to the host (device-to-device through a tensor), then releases it."""
+    res = {}
+    for c in completions:
+        assert c["status"] == 0, c
+        n = int(reqs[c["user_tag"]]["n_blocks"])
+        buf = torch.empty(8 * n, dtype=torch.uint8, device=DEV)
+        _copy_dev(buf.data_ptr(), int(c["dev_out"]), 8 * n)
+        torch.cuda.synchronize()
+        res[int(c["user_tag"])] = buf.cpu().numpy()
+        td.tdes_server_release(server, int(c["id"]))
+    return res
+
+
+_hip = None
+
+
+def _copy_dev(dst, src, nbytes):
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    assert _hip.hipMemcpy(dst, src, nbytes, 3) == 0  # hipMemcpyDeviceToDevice
+
+
+def _check_oracle(keys, req, out, samples=32):
+    n = int(req["n_blocks"])
+    idx = np.unique(np.concatenate([[0, n - 1], np.random.default_rng(int(req["seed"])).integers(0, n, samples)]))
+    k = keys[req["key_id"]]
+    src = inputs.blocks_at(int(req["seed"]), idx)
+    want = _gpu.oracle_on_blocks((k[:8].tobytes(), k[8:16].tobytes(), k[16:].tobytes()), src,
+                                 decrypt=bool(req["direction"]))
+    assert np.array_equal(out.reshape(-1, 8)[idx].reshape(-1), want)
+
+
+def test_alone_equals_in_the_mix(table):
+    keys, dev_table = table
+    reqs = _requests(200, 0x5E02)
+    probe = [3, 50, 77, 150, 199]
+    # Alone: one request at a time through its own server.
+    server = td.tdes_server_create(dev_table, N_KEYS, 1 << 30, max_inflight=2, keep_outputs=True)
+    try:
+        alone = {}
+        for i in probe:
+            td.tdes_server_submit(server, reqs[i])
+            td.tdes_server_wait_idle(server, 60)
+            alone.update(_outputs_by_tag(server, td.tdes_server_poll(server), reqs))
+        assert td.tdes_server_stats(server)["pool_bytes_in_use"] == 0
+    finally:
+        td.tdes_server_destroy(server)
+    # In the mix: all 200 arrive over ~20 ms and overlap on the device.
+    server = td.tdes_server_create(dev_table, N_KEYS, 1 << 30, max_inflight=3, max_step_jobs=64, keep_outputs=True)
+    try:
+        arrival = np.sort(np.random.default_rng(7).uniform(0, 0.02, reqs.size))
+        done = td.tdes_server_run_trace(server, reqs, arrival)
+        assert (done["status"] == 0).all()
+        assert (done["t_complete"] >= done["t_launch"]).all() and (done["t_launch"] >= done["t_admit"]).all()
+        assert (done["t_admit"] >= done["t_arrival"] - 1e-9).all()
+        stats = td.tdes_server_stats(server)
+        assert stats["steps"] > 1 and stats["completed"] == reqs.size
+        mixed = _outputs_by_tag(server, done, reqs)
+        assert td.tdes_server_stats(server)["pool_bytes_in_use"] == 0
+    finally:
+        td.tdes_server_destroy(server)
+    for i in probe:
+        assert np.array_equal(alone[i], mixed[i]), f"request {i} differs alone and in the mix"
+    for i in range(0, reqs.size, 7):
+        _check_oracle(keys, reqs[i], mixed[i])
+
+
+def test_budget_admission_and_cancel(table):
+    keys, dev_table = table
+    budget = 64 << 20
+    reqs = _requests(120, 0x5E03, max_blocks=1 << 19)   # up to 4 MiB each: many will not fit at once
+    server = td.tdes_server_create(dev_table, N_KEYS, budget, max_inflight=2, max_step_jobs=16)
+    try:
+        big = np.zeros(1, dtype=td.REQUEST_DTYPE)
+        big["n_blocks"] = (budget // 16) + 1                 # input + output just over the budget
+        with pytest.raises(td.TdesError) as e:
+            td.tdes_server_submit(server, big)
+        assert e.value.code == -10
+        bad = reqs[:1].copy()
+        bad["key_id"] = N_KEYS
+        with pytest.raises(td.TdesError) as e:
+            td.tdes_server_submit(server, bad)
+        assert e.value.code == -4
+        done = td.tdes_server_run_trace(server, reqs, np.zeros(reqs.size))
+        assert (done["status"] == 0).all()
+        stats = td.tdes_server_stats(server)
+        assert stats["peak_pool_bytes"] <= budget
+        assert stats["completed"] == reqs.size and stats["pool_bytes_in_use"] == 0
+        assert stats["bytes"] == int(reqs["n_blocks"].sum()) * 8
+        # Cancel: fill the budget with one request, queue two more, cancel the last while it waits.
+        fill = np.zeros(1, dtype=td.REQUEST_DTYPE)
+        fill["n_blocks"] = budget // 16 - 4096
+        ids = [td.tdes_server_submit(server, fill), td.tdes_server_submit(server, reqs[0]),
+               td.tdes_server_submit(server, reqs[1])]
+        canceled = True
+        try:
+            td.tdes_server_cancel(server, ids[2])
+        except td.TdesError as err:       # it may already have been admitted
+            assert err.code == -11
+            canceled = False
+        td.tdes_server_wait_idle(server, 60)
+        got = {int(c["id"]): int(c["status"]) for c in td.tdes_server_poll(server)}
+        assert got[ids[0]] == 0 and got[ids[1]] == 0
+        assert got[ids[2]] == (-11 if canceled else 0)
+    finally:
+        td.tdes_server_destroy(server)
+
+
+def test_host_payloads(table):
+    keys, dev_table = table
+    server = td.tdes_server_create(dev_table, N_KEYS, 1 << 28, max_inflight=2)
+    try:
+        n = 5000
+        host_in = inputs.message(0x5E04, n)
+        host_out = np.zeros_like(host_in)
+        req = np.zeros(1, dtype=td.REQUEST_DTYPE)
+        req["n_blocks"] = n
+        req["key_id"] = 9
+        req["direction"] = 1
+        req["host_in"] = host_in.ctypes.data
+        req["host_out"] = host_out.ctypes.data
+        td.tdes_server_submit(server, req)
+        td.tdes_server_wait_idle(server, 60)
+        (c,) = td.tdes_server_poll(server)
+        assert c["status"] == 0 and c["dev_out"] == 0
+        k = keys[9]
+        want = _gpu.oracle_on_blocks((k[:8].tobytes(), k[8:16].tobytes(), k[16:].tobytes()), host_in, decrypt=True)
+        assert np.array_equal(host_out, want)
+    finally:
+        td.tdes_server_destroy(server)
