@@ -1,21 +1,27 @@
-"""Benchmark: Triple-DES (EDE) ECB throughput on one MI355X.
+"""Benchmark: Triple-DES (EDE) ECB on one MI355X.
 
-One step = encrypt one 1 GiB message (2^27 blocks of seeded random bytes,
-HBM-resident) under a random three-key triple, then decrypt the ciphertext:
-one launch each, as in the paper's kernel-only timing (inputs already on the
-device; transfers excluded).  value = plaintext bytes processed per second
-(GB = 1e9 bytes) over the timed steps.
+Timed step (the line's `value`): encrypt one 1 GiB message (2^27 blocks of
+seeded random bytes, resident in HBM) under a random three-key triple, then
+decrypt the ciphertext -- one launch each, kernel-only as in the paper (inputs
+already on the device; transfers excluded).  value = plaintext bytes processed
+per second over the timed steps (GB = 1e9 bytes), with the shipped kernel.
 
-Also reported on the same JSON line:
-  roofline      the dominant kernel against the integer-ALU roofline
-  cpu_baseline  the CPU oracle timed on this host's cores on a bounded sample
-  variants      GB/s of each kernel variant on the same message
+The same JSON line also carries
+  roofline      the shipped kernel against the 32-bit integer ALU peak;
+  variants      GB/s of the table and bitsliced kernels on the same message;
+  batched       4096 messages of log-uniform length, each under its own key:
+                one persistent graph launch against 4096 plain launches;
+  serving       Poisson arrivals of mixed requests at three offered loads:
+                delivered GB/s, p50 / p99 latency;
+  cpu_baseline  the CPU oracle on this host's cores on a bounded sample.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -27,9 +33,13 @@ N_BLOCKS = 1 << 27
 DATA_SEED = 0x3DE50000 + 1
 KEY_SEED = 0x4B455900 + 1
 
-# MI355X: 256 CUs x 64 lanes x 2.4 GHz = 39.32e12 32-bit integer lane-operations per second.
-ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# MI355X integer ALU peak: 256 CUs x 128 32-bit lane-operations per clock x 2.4 GHz
+# (the lane rate behind the published 157.3 TFLOP/s FP32 vector figure, which counts an FMA as 2).
+ALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
+PKG = os.path.join(ROOT, "paper_1305_4376_amd")
+KERNEL_SOURCES = ["csrc/bitslice_core.h", "csrc/k_bitslice.hip", "csrc/sbox_circuits.inc"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tdes_bitslice_kernel_1GiB_traffic.md")
 
 
 def parse():
@@ -38,12 +48,50 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-blocks", type=int, default=1 << 21)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--cpu-sample-blocks", type=int, default=1 << 23)
+    ap.add_argument("--serve-seconds", type=float, default=1.0, help="trace length per offered load")
+    ap.add_argument("--no-host-path", action="store_true")
+    ap.add_argument("--paper-ablation", action="store_true",
+                    help="also time the paper's launch scheme: a 512 MiB message cut into launches of "
+                         "128 .. 2^26 blocks (the analogue of Table II)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one 1 GiB elementwise XOR kernel (1 GiB read + 1 GiB written), the known-size "
+                         "reference that scales the profiler's FETCH_SIZE / WRITE_SIZE counters")
     return ap.parse_args()
 
 
-def time_variant(td, torch, sched, src, ct, pt, variant, steps, warmup):
-    """Wall time of `steps` encrypt+decrypt steps and per-launch HIP-event durations."""
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(PKG, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the shipped kernel from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source; else None."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    m_hash = re.search(r"kernel source hash:\s*([0-9a-f]+)", text)
+    m_bytes = re.search(r"HBM bytes per launch:\s*([0-9.e+]+)", text)
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_hash():
+        return None
+    return float(m_bytes.group(1))
+
+
+def circuit_gates() -> int:
+    """Gates in the shipped S-box circuits (sum over the eight boxes)."""
+    text = open(os.path.join(PKG, "gen", "sbox_circuits.txt")).read()
+    return sum(int(g) for g in re.findall(r"^gates (\d+)", text, flags=re.M))
+
+
+def time_plain(td, torch, sched, src, ct, pt, variant, steps, warmup):
+    """Wall time of `steps` encrypt+decrypt steps and per-launch HIP-event durations (same stream)."""
     for _ in range(warmup):
         td.tdes_ecb_run(sched, src, ct, N_BLOCKS, td.TDES_ENCRYPT, variant)
         td.tdes_ecb_run(sched, ct, pt, N_BLOCKS, td.TDES_DECRYPT, variant)
@@ -59,8 +107,165 @@ def time_variant(td, torch, sched, src, ct, pt, variant, steps, warmup):
         ev[2 * i + 1][1].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    launch_ms = [a.elapsed_time(b) for a, b in ev]
-    return wall, launch_ms
+    return wall, [a.elapsed_time(b) for a, b in ev]
+
+
+def key_table(td, torch, inputs, seed, count, dev):
+    keys = inputs.key_triples(seed, count)
+    import numpy as np
+    host = np.empty(count * td.TDES_SCHED_BYTES, dtype=np.uint8)
+    for i in range(count):
+        k = keys[i]
+        host[i * 768:(i + 1) * 768] = td.tdes_expand_key(k[:8].tobytes(), k[8:16].tobytes(), k[16:].tobytes())
+    table = torch.empty(host.size, dtype=torch.uint8, device=dev)
+    td.tdes_sched_upload(host, table)
+    return table
+
+
+def bench_batched(td, torch, inputs, dev, reps=10):
+    """C4: 4096 messages, log-uniform 1..131072 blocks, own three-key triple each, encrypt."""
+    import numpy as np
+    n_msgs = 4096
+    seed = inputs.DATA_SEED_BASE + 4
+    table = key_table(td, torch, inputs, inputs.KEY_SEED_BASE + 4, n_msgs, dev)
+    lengths = inputs.log_uniform_lengths(seed, n_msgs, 131072)
+    starts = np.concatenate([[0], np.cumsum(lengths)[:-1]]) * 8
+    total = int(lengths.sum()) * 8
+    buf = torch.empty(2 * total, dtype=torch.uint8, device=dev)
+    td.tdes_fill_splitmix64(buf, total // 8, seed, 0)
+    jobs = np.zeros(n_msgs, dtype=td.JOB_DTYPE)
+    jobs["in_off"], jobs["out_off"], jobs["n_blocks"] = starts, starts + total, lengths
+    jobs["sched_idx"] = np.arange(n_msgs)
+    from paper_1305_4376_amd import autotune
+    ctx = td.tdes_ctx_create()
+    try:
+        tuned = autotune.tune_batch(ctx, jobs, table, n_msgs, buf, reps=3, path=None)
+
+        def timed(fn):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) / reps
+        t_plan = timed(lambda: td.tdes_ecb_batch(ctx, jobs, table, n_msgs, buf, 0))
+        t_replay = timed(lambda: td.tdes_ecb_batch_replay(ctx, 0))
+        t_direct = timed(lambda: td.tdes_ecb_batch_replay(ctx, td.TDES_BATCH_NO_GRAPH))
+        out_batched = buf[total:].clone()
+        t_plain = timed(lambda: td.tdes_ecb_batch(ctx, jobs, table, n_msgs, buf, td.TDES_BATCH_PER_MESSAGE))
+        same = bool(torch.equal(buf[total:], out_batched))
+        info = td.tdes_ctx_get_info(ctx)
+    finally:
+        td.tdes_ctx_destroy(ctx)
+    gbs = lambda t: round(total / t / 1e9, 3)
+    return {
+        "workload": "4096 messages, lengths log-uniform 1..131072 blocks, own 3-key triple each, encrypt",
+        "bytes": total,
+        "graph_replay_gbs": gbs(t_replay), "graph_replay_ms": round(t_replay * 1e3, 4),
+        "direct_launch_gbs": gbs(t_direct),
+        "plan_upload_launch_gbs": gbs(t_plan),
+        "per_message_plain_gbs": gbs(t_plain), "per_message_plain_ms": round(t_plain * 1e3, 4),
+        "speedup_vs_per_message": round(t_plain / t_replay, 2),
+        "identical_to_per_message": same,
+        "tiles": info["tiles"], "lane_tiles": info["lane_tiles"],
+        "padding_frac": round(info["padded_blocks"] / info["blocks"] - 1, 4),
+        "launch_shape": [info["threads"], info["groups_per_cu"]],
+        "autotune_ms": {f"{th}x{g}": t for t, th, g in tuned["candidates"][:6]},
+    }, total / t_replay
+
+
+def bench_serving(td, torch, inputs, dev, capacity_bps, seconds):
+    """C5: Poisson arrivals, sizes log-uniform 512 B .. 16 MiB, 50/50 directions, 65536 resident triples,
+    64 GiB admission budget, offered loads 0.5 / 0.8 / 0.95 of the batched capacity."""
+    import numpy as np
+    n_keys = 65536
+    table = key_table(td, torch, inputs, inputs.KEY_SEED_BASE + 5, n_keys, dev)
+    results = []
+    for li, load in enumerate((0.5, 0.8, 0.95)):
+        rng = np.random.default_rng(0x5E5E + li)
+        mean_bytes = 8 * (2 ** 21 - 64) / np.log(2 ** 21 / 64)  # mean of the log-uniform size law
+        lam = load * capacity_bps / mean_bytes
+        n = int(max(2000, min(400000, lam * seconds)))
+        u = rng.random(n)
+        sizes = np.floor(np.exp(np.log(64) + u * (np.log(2 ** 21) - np.log(64)))).astype(np.int64)
+        reqs = np.zeros(n, dtype=td.REQUEST_DTYPE)
+        reqs["n_blocks"] = sizes
+        reqs["key_id"] = rng.integers(0, n_keys, n)
+        reqs["direction"] = rng.integers(0, 2, n)
+        reqs["seed"] = (0x5E000000 + li * 10000000) + np.arange(n)
+        arrival = np.cumsum(rng.exponential(1.0 / lam, n))
+        server = td.tdes_server_create(table, n_keys, 64 << 30, max_inflight=3, max_step_jobs=4096,
+                                       max_step_blocks=1 << 24)
+        try:
+            # Warm-up: the first 5% of the trace (graph captures, plan buffers, first allocations), not measured.
+            n_warm = max(200, n // 20)
+            td.tdes_server_run_trace(server, reqs[:n_warm], arrival[:n_warm] - arrival[0])
+            td.tdes_server_wait_idle(server, 60)
+            done = td.tdes_server_run_trace(server, reqs, arrival)
+            stats = td.tdes_server_stats(server)
+        finally:
+            td.tdes_server_destroy(server)
+        ok = done["status"] == 0
+        lat = (done["t_complete"] - done["t_arrival"])[ok]
+        span = done["t_complete"].max() - done["t_arrival"].min()
+        results.append({
+            "load": load, "requests": n, "offered_gbs": round(lam * mean_bytes / 1e9, 2),
+            "delivered_gbs": round(float(sizes[ok].sum() * 8) / span / 1e9, 2),
+            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+            "failed": int((~ok).sum()), "steps": stats["steps"], "peak_pool_gib": round(stats["peak_pool_bytes"] / 2 ** 30, 3),
+        })
+    return {"workload": "Poisson arrivals, 512 B..16 MiB log-uniform, 50/50 encrypt/decrypt, 65536 resident "
+                        "3-key triples, 64 GiB budget; latency = host-observed completion - scheduled arrival; "
+                        "each load after a warm-up trace of 5% of its requests",
+            "capacity_gbs": round(capacity_bps / 1e9, 2), "loads": results}
+
+
+def bench_host_path(td, torch, sched, dev, reps=3):
+    """A 1 GiB message in pinned host memory: copies in, kernel and copies out overlapped in 64 MiB chunks.
+    PCIe-inclusive; reported beside the kernel-only value, never as it."""
+    n = N_BLOCKS
+    host = torch.empty(n * 8, dtype=torch.uint8).pin_memory()
+    dev_msg = torch.empty(n * 8, dtype=torch.uint8, device=dev)
+    td.tdes_fill_splitmix64(dev_msg, n, DATA_SEED, 0)
+    host.copy_(dev_msg)
+    out = torch.empty_like(host).pin_memory()
+    del dev_msg
+    td.tdes_ecb_host(sched, host, out, n, td.TDES_ENCRYPT, chunk_blocks=1 << 23)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        td.tdes_ecb_host(sched, host, out, n, td.TDES_ENCRYPT, chunk_blocks=1 << 23)
+    dt = (time.perf_counter() - t0) / reps
+    return {"workload": "the 1 GiB message in pinned host memory, encrypt, 64 MiB chunks through 3 device "
+                        "slots (H2D, kernel, D2H on separate streams)", "gbs": round(n * 8 / dt / 1e9, 3),
+            "ms": round(dt * 1e3, 3)}
+
+
+def bench_paper_scheme(td, torch, sched, dev):
+    """The paper's host loop (Listing 1.1): one launch per chunk of a 512 MiB message, swept over the
+    chunk size as in Table II.  At most 1000 launches are timed per size; the total is scaled to the
+    whole message (labelled extrapolated)."""
+    total = 1 << 26  # 512 MiB
+    msg = torch.empty(total * 8, dtype=torch.uint8, device=dev)
+    td.tdes_fill_splitmix64(msg, total, DATA_SEED, 0)
+    rows = []
+    for chunk in (128, 512, 2048, 8192, 32768, 131072, 524288, 1 << 21, 1 << 23, 1 << 26):
+        launches = total // chunk
+        timed = min(launches, 1000)
+        for i in range(min(timed, 20)):
+            td.tdes_ecb_encrypt(sched, msg[i * chunk * 8:], msg[i * chunk * 8:], chunk)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(timed):
+            off = (i % launches) * chunk * 8
+            td.tdes_ecb_encrypt(sched, msg[off:], msg[off:], chunk)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) * launches / timed
+        rows.append({"blocks_per_launch": chunk, "launches": launches, "seconds": round(dt, 5),
+                     "gbs": round(total * 8 / dt / 1e9, 3), "extrapolated": timed < launches})
+    return {"workload": "512 MiB message, in place, one plain launch per chunk (Listing 1.1's loop)",
+            "rows": rows}
 
 
 def cpu_baseline(sample_blocks):
@@ -73,15 +278,16 @@ def cpu_baseline(sample_blocks):
     oracle.tdes_ecb(*keys, data, decrypt=False, threads=cores)
     dt = time.perf_counter() - t0
     return {"value": round(data.size / dt / 1e9, 6), "unit": "GB/s", "cores": cores, "kind": "oracle",
-            "sample": f"encrypt the first {sample_blocks} blocks ({data.size >> 20} MiB) of the same message "
-                      f"with the same key triple, {cores} threads, {dt:.1f} s"}
+            "sample": f"encrypt the first {sample_blocks} blocks ({data.size >> 20} MiB) of the benchmark message "
+                      f"with its key triple on {cores} threads: {dt:.1f} s"}
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); ECB shards need no "
-              "communication, so the whole-job rate is the one-GPU rate times the GPU count.", file=sys.stderr)
+        print(f"bench.py measures one GPU (asked for {args.gpus}): every configuration here runs on a single "
+              "MI355X; ECB shards need no communication, so a G-GPU job runs G independent shards.",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1305_4376_amd as td
@@ -98,37 +304,54 @@ def main():
     ct, pt = torch.empty_like(src), torch.empty_like(src)
     torch.cuda.synchronize()
 
-    variants = {"table": td.TDES_VARIANT_TABLE, "bitslice": td.TDES_VARIANT_BITSLICE}
-    results = {}
-    for name, v in variants.items():
-        wall, launch_ms = time_variant(td, torch, sched, src, ct, pt, v, args.steps, args.warmup)
-        results[name] = (wall, launch_ms)
-    shipped = "table"
-    wall, launch_ms = results[shipped]
-    # The last decrypt must give the message back.
-    ok = bool(torch.equal(pt, src))
+    if args.calib_copy:
+        torch.bitwise_xor(src, 0x5A, out=ct)
+        torch.cuda.synchronize()
 
     bytes_per_step = 2 * N_BLOCKS * 8
+    variants = {}
+    for name, v in (("table", td.TDES_VARIANT_TABLE), ("bitslice", td.TDES_VARIANT_BITSLICE)):
+        wall, _ = time_plain(td, torch, sched, src, ct, pt, v, max(3, args.steps // 4), 1)
+        variants[name] = round(bytes_per_step * max(3, args.steps // 4) / wall / 1e9, 3)
+    # The timed run: the shipped default (TDES_VARIANT_AUTO = bitsliced).
+    wall, launch_ms = time_plain(td, torch, sched, src, ct, pt, td.TDES_VARIANT_AUTO, args.steps, args.warmup)
+    roundtrip_ok = bool(torch.equal(pt, src))
     value = bytes_per_step * args.steps / wall / 1e9
     avg_launch_s = sum(launch_ms) / len(launch_ms) / 1e3
-    # VALU instructions per block of the table kernel's round loop: 15 per round x 48 rounds
-    # (the prologue and epilogue add about 60 more per block and are not counted).
-    ops_per_block = 15 * 48
-    achieved_tops = ops_per_block * N_BLOCKS / avg_launch_s / 1e12
+
+    gates = circuit_gates()
+    ops_per_block = 12 * gates / 8 + 120  # 48 rounds x (48 key XORs + gates + 32 XORs into L) / 32 blocks
+    achieved = ops_per_block * N_BLOCKS / avg_launch_s / 1e12
+    traffic = measured_traffic()
     line = {
         "metric": METRIC, "value": round(value, 3), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-        "config": {"workload": "3DES-EDE ECB, one 1 GiB message (2^27 blocks, SplitMix64 bytes), one 3-key "
+        "config": {"workload": "3DES-EDE ECB, one 1 GiB message (2^27 blocks of SplitMix64 bytes), one 3-key "
                                "triple, encrypt then decrypt per step, one launch each, HBM-resident",
-                   "n_blocks": N_BLOCKS, "keying": 3, "variant": shipped},
-        "roofline": {"bound": "alu", "achieved": round(achieved_tops, 3), "peak": round(ALU_PEAK_TOPS, 3),
-                     "unit": "Tops/s", "frac": round(achieved_tops / ALU_PEAK_TOPS, 4), "traffic": None,
-                     "hbm_frac": round(16 * N_BLOCKS / avg_launch_s / 1e9 / HBM_PEAK_GBS, 4)},
-        "variants": {n: round(bytes_per_step * args.steps / r[0] / 1e9, 3) for n, r in results.items()},
-        "kernel_ms": round(avg_launch_s * 1e3, 4),
-        "roundtrip_ok": ok,
+                   "n_blocks": N_BLOCKS, "keying": 3, "kernel": "bitslice"},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 3),
+                     "unit": "Tops/s", "frac": round(achieved / ALU_PEAK_TOPS, 4),
+                     "traffic": traffic,
+                     "ops_per_block": ops_per_block, "kernel_ms": round(avg_launch_s * 1e3, 4),
+                     "hbm_frac": round(16 * N_BLOCKS / avg_launch_s / 1e9 / HBM_PEAK_GBS, 4),
+                     "kernel_hash": kernel_hash()},
+        "variants": variants,
+        "roundtrip_ok": roundtrip_ok,
     }
+    del ct, pt
+    torch.cuda.empty_cache()
+    if not args.no_host_path:
+        line["host_path"] = bench_host_path(td, torch, sched, dev)
+    if args.paper_ablation:
+        line["paper_scheme"] = bench_paper_scheme(td, torch, sched, dev)
+        torch.cuda.empty_cache()
+    capacity = value * 1e9
+    if not args.no_batched:
+        line["batched"], capacity = bench_batched(td, torch, inputs, dev)
+        torch.cuda.empty_cache()
+    if not args.no_serving:
+        line["serving"] = bench_serving(td, torch, inputs, dev, capacity, args.serve_seconds)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_sample_blocks)
     print(json.dumps(line), flush=True)

@@ -117,6 +117,22 @@ int tdes_ecb_decrypt(const void *dev_sched, const void *in, void *out, uint64_t 
 int tdes_ecb_run(const void *dev_sched, const void *in, void *out, uint64_t n_blocks, int direction,
                  int variant, void *stream);
 
+/*
+ * ECB over a message held in host memory (the paper's setting, Listing 1.1,
+ * with the transfers overlapped instead of done once around the kernels):
+ * chunks of chunk_blocks blocks move through three device buffers; the copy
+ * in, the bitsliced kernel and the copy out each run on their own stream so
+ * that chunks overlap.  Synchronous: returns when host_out holds the result
+ * (work already queued on `stream` is waited for first).  Allocates
+ * 3 * chunk_blocks * 8 bytes of device memory for the duration of the call.
+ * host_in == host_out is allowed.  Host buffers should be pinned
+ * (hipHostMalloc) for the copies to overlap.
+ * Errors: TDES_ERR_NULL, TDES_ERR_ALIGN, TDES_ERR_ARG, TDES_ERR_SIZE
+ * (chunk_blocks 0 or above 2^31), TDES_ERR_OVERLAP, TDES_ERR_NOMEM, TDES_ERR_HIP.
+ */
+int tdes_ecb_host(const void *dev_sched, const void *host_in, void *host_out, uint64_t n_blocks, int direction,
+                  uint64_t chunk_blocks, void *stream);
+
 /* ---- batched ECB: many messages, each with its own key triple and direction ---- */
 
 /*

@@ -23,7 +23,7 @@ __all__ = [
     "tdes_ecb_batch", "tdes_ecb_batch_replay", "tdes_ctx_set_tuning", "tdes_ctx_get_info",
     "REQUEST_DTYPE", "COMPLETION_DTYPE", "tdes_server_create", "tdes_server_destroy", "tdes_server_now",
     "tdes_server_submit", "tdes_server_cancel", "tdes_server_poll", "tdes_server_wait_idle",
-    "tdes_server_release", "tdes_server_stats", "tdes_server_run_trace",
+    "tdes_server_release", "tdes_server_stats", "tdes_server_run_trace", "tdes_ecb_host",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtdes.so")
@@ -112,6 +112,7 @@ def load_library():
         "tdes_server_release": ([vp, u64], i32),
         "tdes_server_stats": ([vp, ctypes.POINTER(_ServeStats)], i32),
         "tdes_server_run_trace": ([vp, vp, vp, u64, vp], i32),
+        "tdes_ecb_host": ([vp, vp, vp, u64, i32, u64, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -306,3 +307,11 @@ def tdes_server_run_trace(server: int, reqs: np.ndarray, arrival_s: np.ndarray) 
     _check(load_library().tdes_server_run_trace(server, r.ctypes.data, a.ctypes.data, int(r.size),
                                                 out.ctypes.data), "tdes_server_run_trace")
     return out
+
+
+def tdes_ecb_host(dev_sched, host_in, host_out, n_blocks=None, direction: int = TDES_ENCRYPT,
+                  chunk_blocks: int = 1 << 23, stream=None) -> None:
+    """ECB over a host-resident message (numpy arrays or pinned tensors), copies overlapped in chunks."""
+    n = _nblocks(host_in, n_blocks) if n_blocks is not None or hasattr(host_in, "numel") else np.asarray(host_in).nbytes // 8
+    _check(load_library().tdes_ecb_host(_ptr(dev_sched), _ptr(host_in), _ptr(host_out), int(n), int(direction),
+                                        int(chunk_blocks), _stream(stream)), "tdes_ecb_host")

@@ -64,7 +64,8 @@ struct tdes_ctx {
     hipGraphExec_t exec = nullptr;
     const void *g_sched = nullptr;
     const void *g_base = nullptr;
-    const void *g_plan = nullptr;
+    const void *g_tiles = nullptr;  // every pointer the kernel node was captured with
+    const void *g_slots = nullptr;
     uint32_t g_grid = 0, g_threads = 0;
     tdes_batch_info info{};
 };
@@ -82,6 +83,12 @@ int ensure_capacity(tdes_ctx *c, size_t tiles, size_t slots) {
     if (c->d_plan) {
         if (hipEventSynchronize(c->plan_done) != hipSuccess) return TDES_ERR_HIP;
         if (hipEventSynchronize(c->staging_free) != hipSuccess) return TDES_ERR_HIP;
+        // The captured graph points into the old buffer (and at the old slot offset, which
+        // moves with the capacity even if the allocator returns the same address): drop it.
+        if (c->exec) {
+            (void)hipGraphExecDestroy(c->exec);
+            c->exec = nullptr;
+        }
         (void)hipFree(c->d_plan);
         (void)hipHostFree(c->h_plan);
         c->d_plan = c->h_plan = nullptr;
@@ -212,8 +219,8 @@ int launch_plan(tdes_ctx *c, const void *sched, uint8_t *base, bool use_graph, h
         if (tdes::launch_batch(ks, hdr, tiles, slots, c->d_counter, base, grid, c->threads, stream) != hipSuccess)
             return TDES_ERR_HIP;
     } else {
-        if (!c->exec || c->g_sched != sched || c->g_base != base || c->g_plan != c->d_plan || c->g_grid != grid ||
-            c->g_threads != c->threads) {
+        if (!c->exec || c->g_sched != sched || c->g_base != base || c->g_tiles != tiles || c->g_slots != slots ||
+            c->g_grid != grid || c->g_threads != c->threads) {
             if (c->exec) {
                 (void)hipGraphExecDestroy(c->exec);
                 c->exec = nullptr;
@@ -236,7 +243,8 @@ int launch_plan(tdes_ctx *c, const void *sched, uint8_t *base, bool use_graph, h
             }
             c->g_sched = sched;
             c->g_base = base;
-            c->g_plan = c->d_plan;
+            c->g_tiles = tiles;
+            c->g_slots = slots;
             c->g_grid = grid;
             c->g_threads = c->threads;
             c->info.graph_captures++;

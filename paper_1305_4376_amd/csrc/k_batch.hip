@@ -8,7 +8,7 @@
 //
 // Two tile kinds, both running the bitsliced core (bitslice_core.h):
 //   wave tile  -- up to 2048 consecutive blocks of one message: one key for the
-//                 whole wave, held in scalar registers;
+//                 whole wave, its masks in scalar registers;
 //   lane tile  -- 64 lane slots of up to 32 blocks each, packed from the short
 //                 remainders of many messages: every lane reads its own slot,
 //                 key and direction (key masks then come from vector registers).
@@ -64,9 +64,9 @@ __global__ __launch_bounds__(kMaxThreads) void tdes_batch_kernel(const uint32_t 
             const bool full = s.count == kTileBlocks &&
                               ((reinterpret_cast<uintptr_t>(tin) | reinterpret_cast<uintptr_t>(tout)) & 15) == 0;
             if (full)
-                wave_tile<true>(ks, tin, tout, kTileBlocks, lane);
+                wave_tile<true, kScalarMasks>(ks, tin, tout, kTileBlocks, lane);
             else
-                wave_tile<false>(ks, tin, tout, s.count, lane);
+                wave_tile<false, kScalarMasks>(ks, tin, tout, s.count, lane);
         }
     }
 }
@@ -78,7 +78,8 @@ namespace tdes {
 hipError_t launch_batch(const uint32_t *sched, const PlanHeader *hdr, const uint32_t *tiles, const Slot *slots,
                         uint32_t *counter, uint8_t *base, uint32_t grid, uint32_t threads, hipStream_t stream) {
     if (threads == 0 || threads > kMaxThreads || threads % kLanes != 0 || grid == 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(tdes_batch_kernel, dim3(grid), dim3(threads), 0, stream, sched, hdr, tiles, slots, counter, base);
+    hipLaunchKernelGGL(tdes_batch_kernel, dim3(grid), dim3(threads), 0, stream, sched, hdr, tiles, slots, counter,
+                       base);
     return hipGetLastError();
 }
 

@@ -7,7 +7,8 @@
 // DES stages of EDE fused in one pass over the data.
 //
 // Launch: one wave per 2048-block tile (16 KiB of the message), four waves
-// per workgroup; tiles beyond 2^22 loop grid-stride.
+// per workgroup; tiles beyond 2^22 loop grid-stride.  The key is the same for
+// the whole launch, so its masks come from scalar registers.
 #include <hip/hip_runtime.h>
 
 #include "bitslice_core.h"
@@ -18,6 +19,7 @@ namespace {
 using namespace tdes_bs;
 
 constexpr int kThreads = 256;  // 4 waves per workgroup
+constexpr KeyMode kWaveKeys = kScalarMasks;
 
 __global__ __launch_bounds__(kThreads) void tdes_bitslice_kernel(const uint32_t *__restrict__ ks, const uint8_t *in,
                                                                  uint8_t *out, uint64_t n_blocks, int vec16) {
@@ -30,9 +32,9 @@ __global__ __launch_bounds__(kThreads) void tdes_bitslice_kernel(const uint32_t 
         const uint64_t left = n_blocks - first;
         const uint32_t n_valid = left < kTileBlocks ? (uint32_t)left : kTileBlocks;
         if (vec16 && n_valid == kTileBlocks)
-            wave_tile<true>(ks, in + 8 * first, out + 8 * first, n_valid, lane);
+            wave_tile<true, kWaveKeys>(ks, in + 8 * first, out + 8 * first, n_valid, lane);
         else
-            wave_tile<false>(ks, in + 8 * first, out + 8 * first, n_valid, lane);
+            wave_tile<false, kWaveKeys>(ks, in + 8 * first, out + 8 * first, n_valid, lane);
     }
 }
 

@@ -337,6 +337,8 @@ void engine_loop(tdes_server *s) {
             const int rc = launch_step(s, st);
             if (rc != TDES_OK) {
                 s->engine_error = rc;
+                // Work already enqueued for this step may still touch its buffers.
+                (void)hipStreamSynchronize(st.stream);
                 // Fail the admitted requests rather than leave them pending.
                 std::lock_guard<std::mutex> lk(s->mu);
                 for (uint64_t id : st.ids) {

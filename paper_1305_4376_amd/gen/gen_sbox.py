@@ -120,18 +120,18 @@ class Circuit:
         return Circuit(gates, outs)
 
 
-def load_store() -> dict[int, Circuit]:
-    if not os.path.exists(STORE):
+def load_store(path: str = STORE) -> dict[int, Circuit]:
+    if not os.path.exists(path):
         return {}
     out = {}
-    for block in re.split(r"^box ", open(STORE).read(), flags=re.M)[1:]:
+    for block in re.split(r"^box ", open(path).read(), flags=re.M)[1:]:
         head, _, body = block.partition("\n")
         out[int(head.split()[0]) - 1] = Circuit.parse(body)
     return out
 
 
-def save_store(circuits: dict[int, Circuit]):
-    with open(STORE, "w") as f:
+def save_store(circuits: dict[int, Circuit], path: str = STORE):
+    with open(path, "w") as f:
         f.write("# S-box circuits of 3-input lookup gates, found by sbox_search.c; see gen_sbox.py.\n")
         f.write("# Nodes 0..5 are the box inputs (0 = first); 'g node a b c table'; 'out' lists the nodes\n")
         f.write("# of output bits 1..4 (an output may be the complement of its node).\n")
@@ -157,24 +157,26 @@ def emit(circuits: dict[int, Circuit], boxes) -> str:
     out = ["// Generated by gen/gen_sbox.py from gen/sbox_circuits.txt; do not edit.",
            "// sbox<b>(x0..x5, o0..o3): o_j ^= output bit j of S-box b+1 for inputs x0..x5",
            "// (x0 = first input bit, o0 = first output bit), 32 lanes of bits at once.",
+           "// sbox<b>_m(x0..x5, o0..o3, m0..m3): o_j ^= output bit j ^ m_j (m_j a key mask, 0 or ~0).",
            "// Each gate is one v_bitop3_b32 (truth table bit 4a+2b+c).", ""]
     total = 0
     for b in range(8):
         c = circuits[b]
         pol = c.polarities(boxes[b])
         total += c.cost()
-        out.append(f"// S{b + 1}: {len(c.gates)} gates, {c.cost()} operations with the output XORs")
-        out.append(f"__device__ __forceinline__ void sbox{b}(uint32_t n0, uint32_t n1, uint32_t n2, uint32_t n3, "
-                   f"uint32_t n4, uint32_t n5, uint32_t &o0, uint32_t &o1, uint32_t &o2, uint32_t &o3) {{")
+        head = (f"uint32_t n0, uint32_t n1, uint32_t n2, uint32_t n3, uint32_t n4, uint32_t n5, "
+                f"uint32_t &o0, uint32_t &o1, uint32_t &o2, uint32_t &o3")
         outs_set = {}
         for j, o in enumerate(c.outs):
             outs_set.setdefault(o, []).append(j)
+        # plain variant: a two-operand output gate also absorbs the XOR into the Feistel plane
+        out.append(f"// S{b + 1}: {len(c.gates)} gates, {c.cost()} operations with the output XORs")
+        out.append(f"__device__ __forceinline__ void sbox{b}({head}) {{")
         folded = set()
         for node, a, bb, cc, lut in c.gates:
             js = outs_set.get(node, [])
             ops = list(dict.fromkeys([a, bb, cc]))
             if len(js) == 1 and len(ops) <= 2 and c.uses(node) == 0:
-                # Fold the XOR into the Feistel plane: o ^= g(a, b) as one gate over (o, a, b).
                 j = js[0]
                 while len(ops) < 2:
                     ops.append(ops[0])
@@ -191,10 +193,16 @@ def emit(circuits: dict[int, Circuit], boxes) -> str:
         for j, o in enumerate(c.outs):
             if j in folded:
                 continue
-            if pol[j]:
-                out.append(f"    o{j} = ~(o{j} ^ n{o});")
-            else:
-                out.append(f"    o{j} ^= n{o};")
+            out.append(f"    o{j} = ~(o{j} ^ n{o});" if pol[j] else f"    o{j} ^= n{o};")
+        out.append("}")
+        out.append("")
+        # masked variant: every output is a three-way XOR (Feistel plane, S-box bit, key mask)
+        out.append(f"__device__ __forceinline__ void sbox{b}_m({head}, uint32_t m0, uint32_t m1, uint32_t m2, "
+                   f"uint32_t m3) {{")
+        for node, a, bb, cc, lut in c.gates:
+            out.append(f"    const uint32_t n{node} = __builtin_amdgcn_bitop3_b32(n{a}, n{bb}, n{cc}, 0x{lut:02X});")
+        for j, o in enumerate(c.outs):
+            out.append(f"    o{j} = __builtin_amdgcn_bitop3_b32(o{j}, n{o}, m{j}, 0x{0x69 if pol[j] else 0x96:02X});")
         out.append("}")
         out.append("")
     out.append(f"// Total over the eight boxes: {total} operations; average {total / 8:.2f}.")
@@ -207,9 +215,11 @@ def main():
     ap.add_argument("--budget", type=int, default=200000)
     ap.add_argument("--seeds", type=int, default=8)
     ap.add_argument("--boxes", default="1,2,3,4,5,6,7,8")
+    ap.add_argument("--store", default=STORE, help="circuit store to read and update")
+    ap.add_argument("--out", default=OUT_INC, help="generated HIP include")
     args = ap.parse_args()
     boxes = sbox_tables()
-    circuits = load_store()
+    circuits = load_store(args.store)
     if args.search:
         exe = build_search()
         todo = [int(b) - 1 for b in args.boxes.split(",")]
@@ -224,15 +234,15 @@ def main():
             if b not in circuits or c.cost() < circuits[b].cost():
                 circuits[b] = c
                 print(f"S{b + 1}: {len(c.gates)} gates, cost {c.cost()}", file=sys.stderr)
-        save_store(circuits)
+        save_store(circuits, args.store)
     missing = [b + 1 for b in range(8) if b not in circuits]
     if missing:
         sys.exit(f"no circuit stored for boxes {missing}; run with --search")
     for b in range(8):
         circuits[b].polarities(boxes[b])
-    with open(OUT_INC, "w") as f:
+    with open(args.out, "w") as f:
         f.write(emit(circuits, boxes))
-    print(f"wrote {OUT_INC}: total cost {sum(c.cost() for c in circuits.values())}")
+    print(f"wrote {args.out}: total cost {sum(c.cost() for c in circuits.values())}")
 
 
 if __name__ == "__main__":

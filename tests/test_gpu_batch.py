@@ -200,3 +200,25 @@ def test_batch_tuning_shapes(shape):
         _check_jobs(jobs, keys, buf, 0xB33, sample_per_job=48)
     finally:
         td.tdes_ctx_destroy(ctx)
+
+
+def test_plan_growth_after_graph_capture():
+    """A batch larger than the context's plan buffers reallocates them after a graph was captured;
+    the next launch must use a graph captured for the new buffers (the slot array's offset moves
+    with the capacity even when the allocator returns the same address)."""
+    keys, table = _table(16, 0xB41)
+    big = inputs.log_uniform_lengths(0xB42, 3000, 131072)
+    jobs_big, buf, _ = _layout(big, 0xB43)
+    jobs_big["sched_idx"] = np.arange(big.size) % 16
+    small = jobs_big[:3].copy()
+    ctx = td.tdes_ctx_create()
+    try:
+        td.tdes_ecb_batch(ctx, small, table, 16, buf, 0)    # small plan, graph captured
+        torch.cuda.synchronize()
+        captures = td.tdes_ctx_get_info(ctx)["graph_captures"]
+        td.tdes_ecb_batch(ctx, jobs_big, table, 16, buf, 0)  # grows the plan buffers
+        torch.cuda.synchronize()
+        assert td.tdes_ctx_get_info(ctx)["graph_captures"] == captures + 1
+        _check_jobs(jobs_big, keys, buf, 0xB43, sample_per_job=8)
+    finally:
+        td.tdes_ctx_destroy(ctx)

@@ -166,3 +166,23 @@ def test_c2_one_gib_sampled(variant):
     assert bool(torch.equal(pt, src))
     del pt, ct, src
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("pinned", [True, False])
+def test_host_resident_message(pinned):
+    """A message in host memory, copies and kernels pipelined in chunks (a ragged last chunk)."""
+    n = 3 * (1 << 16) + 12345
+    keys = inputs.key_triple(0x860)
+    sched = _gpu.device_sched(*keys)
+    host = inputs.message(0x960, n)
+    if pinned:
+        src = torch.from_numpy(host).pin_memory()
+        dst = torch.empty_like(src).pin_memory()
+    else:
+        src, dst = host.copy(), np.zeros_like(host)
+    td.tdes_ecb_host(sched, src, dst, n, td.TDES_ENCRYPT, chunk_blocks=1 << 16)
+    out = dst.numpy() if pinned else dst
+    assert np.array_equal(out, _gpu.oracle_on_blocks(keys, host, False))
+    # in place, decrypting back
+    td.tdes_ecb_host(sched, dst, dst, n, td.TDES_DECRYPT, chunk_blocks=40000)
+    assert np.array_equal(dst.numpy() if pinned else dst, host)

@@ -165,3 +165,14 @@ def test_struct_layouts_match_the_header(tmp_path):
             ct.sizeof(td._ServeConfig), ct.sizeof(td._ServeStats), td.REQUEST_DTYPE.fields["host_out"][1],
             td.COMPLETION_DTYPE.fields["t_complete"][1], td.TDES_SCHED_BYTES]
     assert got == want
+
+
+def test_host_path_argument_errors():
+    lib = td.load_library()
+    s, a, b = 0x10000, 0x200000, 0x400000
+    assert lib.tdes_ecb_host(s, a, b, 0, 0, 1, None) == 0          # nothing to do
+    assert lib.tdes_ecb_host(None, a, b, 8, 0, 1, None) == -1
+    assert lib.tdes_ecb_host(s + 2, a, b, 8, 0, 1, None) == -2
+    assert lib.tdes_ecb_host(s, a, b, 8, 5, 1, None) == -7
+    assert lib.tdes_ecb_host(s, a, b, 8, 0, 0, None) == -4
+    assert lib.tdes_ecb_host(s, a, a + 8, 8, 0, 4, None) == -3
