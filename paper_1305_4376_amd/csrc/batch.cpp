@@ -59,7 +59,7 @@ struct tdes_ctx {
     uint32_t last_tiles = 0;
     // Launch shape.
     uint32_t threads = 256;
-    uint32_t groups_per_cu = 3;
+    uint32_t groups_per_cu = 4;
     // Captured graph and what it was captured for.
     hipGraphExec_t exec = nullptr;
     const void *g_sched = nullptr;

@@ -155,248 +155,12 @@ __device__ __forceinline__ void des_stage(uint32_t (&x)[32], uint32_t (&y)[32], 
 
 // ---- kernel ----
 
-// ---- rounds with folded key masks (one key for the whole wave) ----
-//
-// Between rounds, every plane of a half is kept XORed with the key bit that the
-// next round reading it applies at the plane's first E position.  Then
-//   - the first E use of a plane needs no key XOR;
-//   - a second E use (16 of the 32 bits are read twice) needs one XOR with the
-//     difference of its two key bits;
-//   - XORing an S-box output into the target half also swaps that half's
-//     folded key from round r-1's to round r+1's: one three-way XOR with the
-//     mask of (k[r-1] ^ k[r+1]), replacing the plain XOR of the output.
-// Each DES stage starts with both halves clean (the half read first gets round
-// 0's key folded in) and ends clean (the half read last has round 15's key
-// removed): 64 XORs per stage against 32 saved per round.
-
-struct UseMaps {
-    int first[32];   // first S-box input position (0..47) reading R bit q
-    int second[32];  // second one, or -1
-};
-
-constexpr UseMaps make_uses() {
-    UseMaps u{};
-    for (int q = 0; q < 32; q++) u.first[q] = u.second[q] = -1;
-    for (int i = 0; i < 48; i++) {
-        const int q = tdes_spec::expansion(i);
-        if (u.first[q] < 0) u.first[q] = i; else u.second[q] = i;
-    }
-    return u;
-}
-
-constexpr UseMaps kUses = make_uses();
-
-// Mask of the key bit at S-box input position i (box i / 6) of a round with words (ka, kb).
-__device__ __forceinline__ uint32_t key_bit(uint32_t ka, uint32_t kb, int i) {
-    return key_mask((i / 6) % 2 ? kb : ka, key_pos(i / 6, i % 6));
-}
-
-template <int S>
-__device__ __forceinline__ void sbox_round_folded(uint32_t (&x)[32], const uint32_t (&y)[32], uint32_t ka_in,
-                                                  uint32_t kb_in, uint32_t pa_in, uint32_t pb_in) {
-    const uint32_t ka = key_word<false>(ka_in), kb = key_word<false>(kb_in);
-    const uint32_t pa = key_word<false>(pa_in), pb = key_word<false>(pb_in);
-    uint32_t in[6];
-#pragma unroll
-    for (int j = 0; j < 6; j++) {
-        const int i = 6 * S + j, q = kMaps.e[i];
-        in[j] = kUses.first[q] == i ? y[q] : y[q] ^ (key_bit(ka, kb, kUses.first[q]) ^ key_bit(ka, kb, i));
-    }
-    constexpr int p0 = kMaps.p_inv[4 * S + 0], p1 = kMaps.p_inv[4 * S + 1];
-    constexpr int p2 = kMaps.p_inv[4 * S + 2], p3 = kMaps.p_inv[4 * S + 3];
-    const uint32_t m0 = key_bit(pa, pb, kUses.first[p0]), m1 = key_bit(pa, pb, kUses.first[p1]);
-    const uint32_t m2 = key_bit(pa, pb, kUses.first[p2]), m3 = key_bit(pa, pb, kUses.first[p3]);
-    if constexpr (S == 0) sbox0_m(in[0], in[1], in[2], in[3], in[4], in[5], x[p0], x[p1], x[p2], x[p3], m0, m1, m2, m3);
-    if constexpr (S == 1) sbox1_m(in[0], in[1], in[2], in[3], in[4], in[5], x[p0], x[p1], x[p2], x[p3], m0, m1, m2, m3);
-    if constexpr (S == 2) sbox2_m(in[0], in[1], in[2], in[3], in[4], in[5], x[p0], x[p1], x[p2], x[p3], m0, m1, m2, m3);
-    if constexpr (S == 3) sbox3_m(in[0], in[1], in[2], in[3], in[4], in[5], x[p0], x[p1], x[p2], x[p3], m0, m1, m2, m3);
-    if constexpr (S == 4) sbox4_m(in[0], in[1], in[2], in[3], in[4], in[5], x[p0], x[p1], x[p2], x[p3], m0, m1, m2, m3);
-    if constexpr (S == 5) sbox5_m(in[0], in[1], in[2], in[3], in[4], in[5], x[p0], x[p1], x[p2], x[p3], m0, m1, m2, m3);
-    if constexpr (S == 6) sbox6_m(in[0], in[1], in[2], in[3], in[4], in[5], x[p0], x[p1], x[p2], x[p3], m0, m1, m2, m3);
-    if constexpr (S == 7) sbox7_m(in[0], in[1], in[2], in[3], in[4], in[5], x[p0], x[p1], x[p2], x[p3], m0, m1, m2, m3);
-}
-
-// x ^= f(y) for a round with words (ka, kb); (pa, pb) = previous round's words ^ next round's.
-__device__ __forceinline__ void feistel_folded(uint32_t (&x)[32], const uint32_t (&y)[32], uint32_t ka, uint32_t kb,
-                                               uint32_t pa, uint32_t pb) {
-    sbox_round_folded<0>(x, y, ka, kb, pa, pb);
-    sbox_round_folded<1>(x, y, ka, kb, pa, pb);
-    sbox_round_folded<2>(x, y, ka, kb, pa, pb);
-    sbox_round_folded<3>(x, y, ka, kb, pa, pb);
-    sbox_round_folded<4>(x, y, ka, kb, pa, pb);
-    sbox_round_folded<5>(x, y, ka, kb, pa, pb);
-    sbox_round_folded<6>(x, y, ka, kb, pa, pb);
-    sbox_round_folded<7>(x, y, ka, kb, pa, pb);
-}
-
-// XOR the key bits of round words (ka, kb) at every plane's first E position.
-__device__ __forceinline__ void fold_keys(uint32_t (&h)[32], uint32_t ka_in, uint32_t kb_in) {
-    const uint32_t ka = key_word<false>(ka_in), kb = key_word<false>(kb_in);
-#pragma unroll
-    for (int q = 0; q < 32; q++) h[q] ^= key_bit(ka, kb, kUses.first[q]);
-}
-
-// Sixteen rounds with a wave-uniform key: x holds L0 and y holds R0 on entry,
-// L16 and R16 on exit (both without folded keys).
-__device__ __forceinline__ void des_stage_folded(uint32_t (&x)[32], uint32_t (&y)[32], const uint32_t *__restrict__ ks) {
-    fold_keys(y, ks[0], ks[1]);
-    uint32_t prev_a = 0, prev_b = 0;  // round r-1's words (none before round 0)
-#pragma unroll 1
-    for (int r = 0; r < 16; r += 2) {
-        const uint32_t ka0 = ks[2 * r], kb0 = ks[2 * r + 1];
-        const uint32_t ka1 = ks[2 * r + 2], kb1 = ks[2 * r + 3];
-        // Round r + 2's words, or none after round 15 (the index is clamped so the load stays in the stage).
-        const int n2 = r + 2 < 16 ? 2 * r + 4 : 30;
-        const uint32_t ka2 = r + 2 < 16 ? ks[n2] : 0u, kb2 = r + 2 < 16 ? ks[n2 + 1] : 0u;
-        feistel_folded(x, y, ka0, kb0, prev_a ^ ka1, prev_b ^ kb1);
-        feistel_folded(y, x, ka1, kb1, ka0 ^ ka2, kb0 ^ kb2);
-        prev_a = ka1;
-        prev_b = kb1;
-    }
-    fold_keys(x, ks[30], ks[31]);
-}
-
-// ---- the same rounds with every key mask precomputed in LDS ----
-//
-// Extracting each mask from the schedule words costs scalar instructions (one
-// bit-field extract per mask, three per correction), which the compute unit's
-// single scalar unit issues at half the rate of its vector instructions.  The
-// table below holds every mask of one direction (48 rounds x 8 boxes x 8 words,
-// then each stage's two fix-up rows of 32), built once per workgroup; a round
-// reads its masks with two broadcast 16-byte LDS reads per S-box.
-//   round r, box S, word w: w < 4  mask of output w (k[r-1] ^ k[r+1] at the
-//                                  first E position of the plane it updates);
-//                           w >= 4 correction of the box's (w-4)-th second-use
-//                                  input (k[r] at the plane's first E position
-//                                  ^ k[r] at this one), or 0.
-constexpr int kMaskRoundWords = 64;
-constexpr int kMaskFixOffset = 48 * kMaskRoundWords;
-constexpr int kMaskWords = kMaskFixOffset + 3 * 64;
-// 16-byte LDS reads: rows and per-wave tables stay 16-byte aligned.
-static_assert(kMaskRoundWords % 8 == 0 && kMaskFixOffset % 4 == 0 && kMaskWords % 4 == 0, "mask table alignment");
-
-struct SecondUses {
-    int j[8][4];  // box S: the inputs j that are second uses, in order (-1 past the end)
-};
-
-constexpr SecondUses make_second_uses() {
-    SecondUses u{};
-    for (int b = 0; b < 8; b++) {
-        int t = 0;
-        for (int k = 0; k < 4; k++) u.j[b][k] = -1;
-        for (int jj = 0; jj < 6; jj++) {
-            const int i = 6 * b + jj;
-            if (kUses.first[kMaps.e[i]] != i) u.j[b][t++] = jj;
-        }
-    }
-    return u;
-}
-
-constexpr SecondUses kSecond = make_second_uses();
-
-// Cooperative build of the mask table of one direction (ks: its 96 words).
-__device__ __forceinline__ void build_mask_table(uint32_t *tab, const uint32_t *__restrict__ ks, int tid, int nthreads) {
-    for (int w = tid; w < kMaskWords; w += nthreads) {
-        uint32_t m = 0;
-        if (w < kMaskFixOffset) {
-            const int r = w / kMaskRoundWords, b = (w % kMaskRoundWords) / 8, slot = w % 8;
-            const int i = r % 16;
-            if (slot < 4) {
-                const int q = kMaps.p_inv[4 * b + slot];
-                const uint32_t pa = (i > 0 ? ks[2 * r - 2] : 0u) ^ (i < 15 ? ks[2 * r + 2] : 0u);
-                const uint32_t pb = (i > 0 ? ks[2 * r - 1] : 0u) ^ (i < 15 ? ks[2 * r + 3] : 0u);
-                m = key_bit(pa, pb, kUses.first[q]);
-            } else if (kSecond.j[b][slot - 4] >= 0) {
-                const int in = 6 * b + kSecond.j[b][slot - 4];
-                const uint32_t ka = ks[2 * r], kb = ks[2 * r + 1];
-                m = key_bit(ka, kb, kUses.first[kMaps.e[in]]) ^ key_bit(ka, kb, in);
-            }
-        } else {
-            const int f = w - kMaskFixOffset, stage = f / 64, post = (f % 64) / 32, q = f % 32;
-            const int r = 16 * stage + (post ? 15 : 0);
-            m = key_bit(ks[2 * r], ks[2 * r + 1], kUses.first[q]);
-        }
-        tab[w] = m;
-    }
-}
-
-template <int S>
-__device__ __forceinline__ void sbox_round_tab(uint32_t (&x)[32], const uint32_t (&y)[32], const uint32_t *rt) {
-    const uint4 mo = *reinterpret_cast<const uint4 *>(rt + 8 * S);
-    const uint4 mc = *reinterpret_cast<const uint4 *>(rt + 8 * S + 4);
-    const uint32_t corr[4] = {mc.x, mc.y, mc.z, mc.w};
-    uint32_t in[6];
-    int t = 0;
-#pragma unroll
-    for (int j = 0; j < 6; j++) {
-        const int i = 6 * S + j, q = kMaps.e[i];
-        if (kUses.first[q] == i) {
-            in[j] = y[q];
-        } else {
-            in[j] = y[q] ^ corr[t];
-            t++;
-        }
-    }
-    constexpr int p0 = kMaps.p_inv[4 * S + 0], p1 = kMaps.p_inv[4 * S + 1];
-    constexpr int p2 = kMaps.p_inv[4 * S + 2], p3 = kMaps.p_inv[4 * S + 3];
-    if constexpr (S == 0) sbox0_m(in[0], in[1], in[2], in[3], in[4], in[5], x[p0], x[p1], x[p2], x[p3], mo.x, mo.y, mo.z, mo.w);
-    if constexpr (S == 1) sbox1_m(in[0], in[1], in[2], in[3], in[4], in[5], x[p0], x[p1], x[p2], x[p3], mo.x, mo.y, mo.z, mo.w);
-    if constexpr (S == 2) sbox2_m(in[0], in[1], in[2], in[3], in[4], in[5], x[p0], x[p1], x[p2], x[p3], mo.x, mo.y, mo.z, mo.w);
-    if constexpr (S == 3) sbox3_m(in[0], in[1], in[2], in[3], in[4], in[5], x[p0], x[p1], x[p2], x[p3], mo.x, mo.y, mo.z, mo.w);
-    if constexpr (S == 4) sbox4_m(in[0], in[1], in[2], in[3], in[4], in[5], x[p0], x[p1], x[p2], x[p3], mo.x, mo.y, mo.z, mo.w);
-    if constexpr (S == 5) sbox5_m(in[0], in[1], in[2], in[3], in[4], in[5], x[p0], x[p1], x[p2], x[p3], mo.x, mo.y, mo.z, mo.w);
-    if constexpr (S == 6) sbox6_m(in[0], in[1], in[2], in[3], in[4], in[5], x[p0], x[p1], x[p2], x[p3], mo.x, mo.y, mo.z, mo.w);
-    if constexpr (S == 7) sbox7_m(in[0], in[1], in[2], in[3], in[4], in[5], x[p0], x[p1], x[p2], x[p3], mo.x, mo.y, mo.z, mo.w);
-}
-
-__device__ __forceinline__ void feistel_tab(uint32_t (&x)[32], const uint32_t (&y)[32], const uint32_t *rt) {
-    sbox_round_tab<0>(x, y, rt);
-    sbox_round_tab<1>(x, y, rt);
-    sbox_round_tab<2>(x, y, rt);
-    sbox_round_tab<3>(x, y, rt);
-    sbox_round_tab<4>(x, y, rt);
-    sbox_round_tab<5>(x, y, rt);
-    sbox_round_tab<6>(x, y, rt);
-    sbox_round_tab<7>(x, y, rt);
-}
-
-__device__ __forceinline__ void fold_tab(uint32_t (&h)[32], const uint32_t *fix) {
-#pragma unroll
-    for (int q = 0; q < 32; q += 4) {
-        const uint4 m = *reinterpret_cast<const uint4 *>(fix + q);
-        h[q] ^= m.x; h[q + 1] ^= m.y; h[q + 2] ^= m.z; h[q + 3] ^= m.w;
-    }
-}
-
-// Stage `stage` (0..2) of EDE with masks from the table: as des_stage_folded.
-__device__ __forceinline__ void des_stage_tab(uint32_t (&x)[32], uint32_t (&y)[32], const uint32_t *tab, int stage) {
-    fold_tab(y, tab + kMaskFixOffset + 64 * stage);
-    const uint32_t *rt = tab + 16 * stage * kMaskRoundWords;
-#pragma unroll 1
-    for (int r = 0; r < 16; r += 2) {
-        feistel_tab(x, y, rt + r * kMaskRoundWords);
-        feistel_tab(y, x, rt + (r + 1) * kMaskRoundWords);
-    }
-    fold_tab(x, tab + kMaskFixOffset + 64 * stage + 32);
-}
-
 // The whole EDE (or its inverse, by the schedule) on 32 blocks held as two
 // arrays of little-endian words: a[j] = bytes 0..3 and b[j] = bytes 4..7 of
-// block j.  ks: the 96 schedule words of one direction.
-// How the 48 rounds get their key masks:
-//   kLaneMasks   per-lane keys: masks extracted from vector registers (lane tiles);
-//   kScalarMasks one key per wave, one scalar extract and one XOR per S-box input;
-//   kFoldedMasks one key per wave, masks folded into the Feistel XOR (scalar extracts);
-//   kTableMasks  as kFoldedMasks with every mask precomputed in an LDS table.
-enum KeyMode { kLaneMasks, kScalarMasks, kFoldedMasks, kTableMasks };
-
-// The whole EDE (or its inverse, by the schedule) on 32 blocks held as two
-// arrays of little-endian words: a[j] = bytes 0..3 and b[j] = bytes 4..7 of
-// block j.  ks: the 96 schedule words of one direction; tab: the mask table
-// (kTableMasks only).
-template <KeyMode kMode>
-__device__ __forceinline__ void tdes_32_blocks(uint32_t (&a)[32], uint32_t (&b)[32], const uint32_t *__restrict__ ks,
-                                               const uint32_t *tab) {
+// block j.  ks: the 96 schedule words of one direction, wave-uniform
+// (kLaneKeys = false) or per lane (kLaneKeys = true).
+template <bool kLaneKeys>
+__device__ __forceinline__ void tdes_32_blocks(uint32_t (&a)[32], uint32_t (&b)[32], const uint32_t *__restrict__ ks) {
     transpose32(a);
     transpose32(b);
     uint32_t l[32], r[32];
@@ -406,19 +170,19 @@ __device__ __forceinline__ void tdes_32_blocks(uint32_t (&a)[32], uint32_t (&b)[
         l[k] = pl < 32 ? a[pl] : b[pl - 32];
         r[k] = pr < 32 ? a[pr] : b[pr - 32];
     }
-    // Three DES stages; between them IP^-1 then IP cancel and only the halves swap.
-    if constexpr (kMode == kLaneMasks || kMode == kScalarMasks) {
-        des_stage<kMode == kLaneMasks>(l, r, ks);
-        des_stage<kMode == kLaneMasks>(r, l, ks + 32);
-        des_stage<kMode == kLaneMasks>(l, r, ks + 64);
-    } else if constexpr (kMode == kFoldedMasks) {
-        des_stage_folded(l, r, ks);
-        des_stage_folded(r, l, ks + 32);
-        des_stage_folded(l, r, ks + 64);
-    } else {
-        des_stage_tab(l, r, tab, 0);
-        des_stage_tab(r, l, tab, 1);
-        des_stage_tab(l, r, tab, 2);
+    // Three DES stages; between them IP^-1 then IP cancel and only the halves
+    // swap.  One loop runs all three, so the round code exists once.
+#pragma unroll 1
+    for (int stage = 0; stage < 3; stage++) {
+        des_stage<kLaneKeys>(l, r, ks + 32 * stage);
+        if (stage < 2) {
+#pragma unroll
+            for (int k = 0; k < 32; k++) {
+                const uint32_t t = l[k];
+                l[k] = r[k];
+                r[k] = t;
+            }
+        }
     }
     // Preoutput R16 || L16 = (r, l); FP is a renaming back to block bit planes.
 #pragma unroll
@@ -441,40 +205,41 @@ __device__ __forceinline__ uint32_t opaque(uint32_t v) {
 
 // A wave tile: 2048 consecutive blocks starting at `tin`/`tout` (wave-uniform);
 // lane l holds blocks 128k + 2l and 128k + 2l + 1 (k = 0..15), so each access is
-// 16 bytes per lane over 1 KiB contiguous across the wave.  A short tile
-// (n_valid < 2048, or buffers not 16-byte aligned) reads 8 bytes per block,
-// clamping indices past the end to the last valid block, and writes only
-// valid blocks.
-template <bool kFull, KeyMode kMode>
+// 16 bytes per lane over 1 KiB contiguous across the wave.  kFull: all 2048
+// blocks valid and both buffers 16-byte aligned.  Otherwise (n_valid < 2048,
+// or buffers only 8-byte aligned) each block is loaded and stored on its own,
+// at the same addresses, only if it is one of the first n_valid; lanes past
+// the end compute on zeros.
+template <bool kFull>
 __device__ __forceinline__ void wave_tile(const uint32_t *__restrict__ ks, const uint8_t *tin, uint8_t *tout,
-                                          uint32_t n_valid, uint32_t lane, const uint32_t *tab = nullptr) {
+                                          uint32_t n_valid, uint32_t lane) {
     uint32_t a[32], b[32];
     lane = opaque(lane);
 #pragma unroll
     for (int k = 0; k < 16; k++) {
+        const uint8_t *p = tin + 1024 * k + 16 * lane;
         if (kFull) {
-            const uint4 v = *reinterpret_cast<const uint4 *>(tin + 1024 * k + 16 * lane);
+            const uint4 v = *reinterpret_cast<const uint4 *>(p);
             a[2 * k] = v.x; b[2 * k] = v.y; a[2 * k + 1] = v.z; b[2 * k + 1] = v.w;
         } else {
             const uint32_t j = 128 * k + 2 * lane;
-            const uint32_t j0 = j < n_valid ? j : n_valid - 1;
-            const uint32_t j1 = j + 1 < n_valid ? j + 1 : n_valid - 1;
-            const uint2 v0 = *reinterpret_cast<const uint2 *>(tin + 8 * j0);
-            const uint2 v1 = *reinterpret_cast<const uint2 *>(tin + 8 * j1);
+            uint2 v0 = make_uint2(0, 0), v1 = make_uint2(0, 0);
+            if (j < n_valid) v0 = *reinterpret_cast<const uint2 *>(p);
+            if (j + 1 < n_valid) v1 = *reinterpret_cast<const uint2 *>(p + 8);
             a[2 * k] = v0.x; b[2 * k] = v0.y; a[2 * k + 1] = v1.x; b[2 * k + 1] = v1.y;
         }
     }
-    tdes_32_blocks<kMode>(a, b, ks, tab);
+    tdes_32_blocks<false>(a, b, ks);
     lane = opaque(lane);
 #pragma unroll
     for (int k = 0; k < 16; k++) {
+        uint8_t *p = tout + 1024 * k + 16 * lane;
         if (kFull) {
-            *reinterpret_cast<uint4 *>(tout + 1024 * k + 16 * lane) =
-                make_uint4(a[2 * k], b[2 * k], a[2 * k + 1], b[2 * k + 1]);
+            *reinterpret_cast<uint4 *>(p) = make_uint4(a[2 * k], b[2 * k], a[2 * k + 1], b[2 * k + 1]);
         } else {
             const uint32_t j = 128 * k + 2 * lane;
-            if (j < n_valid) *reinterpret_cast<uint2 *>(tout + 8 * j) = make_uint2(a[2 * k], b[2 * k]);
-            if (j + 1 < n_valid) *reinterpret_cast<uint2 *>(tout + 8 * (j + 1)) = make_uint2(a[2 * k + 1], b[2 * k + 1]);
+            if (j < n_valid) *reinterpret_cast<uint2 *>(p) = make_uint2(a[2 * k], b[2 * k]);
+            if (j + 1 < n_valid) *reinterpret_cast<uint2 *>(p + 8) = make_uint2(a[2 * k + 1], b[2 * k + 1]);
         }
     }
 }
@@ -494,7 +259,7 @@ __device__ __forceinline__ void lane_slot(const uint32_t *ks, const uint8_t *lin
 #pragma unroll
         for (int j = 0; j < 32; j++) a[j] = b[j] = 0;
     }
-    tdes_32_blocks<kLaneMasks>(a, b, ks, nullptr);
+    tdes_32_blocks<true>(a, b, ks);
     if (count) {
 #pragma unroll
         for (int j = 0; j < 32; j++)

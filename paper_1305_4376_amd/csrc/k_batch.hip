@@ -29,12 +29,20 @@ namespace {
 using namespace tdes_bs;
 
 constexpr int kMaxThreads = 256;
+// Register budget of four 256-thread workgroups per CU (4 waves per SIMD, at
+// most 128 VGPRs): the rounds of every tile kind fit it without spills; the
+// lane tiles' per-lane load and store phases spill a few values to scratch.
+constexpr int kMinGroupsPerCU = 4;
 
-__global__ __launch_bounds__(kMaxThreads) void tdes_batch_kernel(const uint32_t *__restrict__ sched,
-                                                                 const tdes::PlanHeader *__restrict__ hdr,
-                                                                 const uint32_t *__restrict__ tiles,
-                                                                 const tdes::Slot *__restrict__ slots,
-                                                                 uint32_t *counter, uint8_t *base) {
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__global__ __launch_bounds__(kMaxThreads, kMinGroupsPerCU) void tdes_batch_kernel(
+    const uint32_t *__restrict__ sched, const tdes::PlanHeader *__restrict__ hdr, const uint32_t *__restrict__ tiles,
+    const tdes::Slot *__restrict__ slots, uint32_t *counter, uint8_t *base) {
     const uint32_t lane = threadIdx.x % kLanes;
     const uint32_t n_tiles = hdr->n_tiles;
     const uint32_t n_slots = hdr->n_slots;
@@ -48,7 +56,7 @@ __global__ __launch_bounds__(kMaxThreads) void tdes_batch_kernel(const uint32_t 
                 __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             break;
         }
-        const uint32_t t = tiles[ticket];
+        const uint32_t t = __builtin_amdgcn_readfirstlane(tiles[ticket]);
         const uint32_t first_slot = t & ~tdes::kLaneTileBit;
         if (t & tdes::kLaneTileBit) {
             // Lane tile: 64 slots, one per lane.
@@ -57,16 +65,19 @@ __global__ __launch_bounds__(kMaxThreads) void tdes_batch_kernel(const uint32_t 
             lane_slot(sched + s.ks_off, base + s.in_off, base + s.out_off, s.count);
         } else {
             if (first_slot >= n_slots) continue;
-            const tdes::Slot s = slots[first_slot];
-            const uint32_t *ks = sched + s.ks_off;
-            const uint8_t *tin = base + s.in_off;
-            uint8_t *tout = base + s.out_off;
-            const bool full = s.count == kTileBlocks &&
+            // The slot is the same for the whole wave: keep its fields in scalar registers.
+            const tdes::Slot &sl = slots[first_slot];
+            const uint64_t in_off = uniform64(sl.in_off), out_off = uniform64(sl.out_off);
+            const uint32_t count = __builtin_amdgcn_readfirstlane(sl.count);
+            const uint32_t *ks = sched + __builtin_amdgcn_readfirstlane(sl.ks_off);
+            const uint8_t *tin = base + in_off;
+            uint8_t *tout = base + out_off;
+            const bool full = count == kTileBlocks &&
                               ((reinterpret_cast<uintptr_t>(tin) | reinterpret_cast<uintptr_t>(tout)) & 15) == 0;
             if (full)
-                wave_tile<true, kScalarMasks>(ks, tin, tout, kTileBlocks, lane);
+                wave_tile<true>(ks, tin, tout, kTileBlocks, lane);
             else
-                wave_tile<false, kScalarMasks>(ks, tin, tout, s.count, lane);
+                wave_tile<false>(ks, tin, tout, count, lane);
         }
     }
 }

@@ -6,9 +6,13 @@
 // tables and no LDS, a fixed data-independent cost per block, and the three
 // DES stages of EDE fused in one pass over the data.
 //
-// Launch: one wave per 2048-block tile (16 KiB of the message), four waves
-// per workgroup; tiles beyond 2^22 loop grid-stride.  The key is the same for
-// the whole launch, so its masks come from scalar registers.
+// Two kernels.  The main one takes every whole 2048-block tile (16 KiB of the
+// message, one wave each) of a message whose buffers are 16-byte aligned; its
+// code has only that path, so it fits 128 VGPRs and runs four waves per SIMD.
+// The tail kernel takes the last partial tile, or every tile when a buffer is
+// only 8-byte aligned, with per-block loads and stores.  Tiles beyond 2^22
+// per launch loop grid-stride.  The key is the same for the whole launch, so
+// its masks come from scalar registers.
 #include <hip/hip_runtime.h>
 
 #include "bitslice_core.h"
@@ -18,24 +22,42 @@ namespace {
 
 using namespace tdes_bs;
 
-constexpr int kThreads = 256;  // 4 waves per workgroup
-constexpr KeyMode kWaveKeys = kScalarMasks;
+constexpr int kThreads = 256;            // 4 waves per workgroup
+constexpr int kWaves = kThreads / kLanes;
+constexpr int kMainGroupsPerCU = 4;      // 16 waves per CU: at most 128 VGPRs per lane
+constexpr uint64_t kMaxGrid = 1u << 20;
 
-__global__ __launch_bounds__(kThreads) void tdes_bitslice_kernel(const uint32_t *__restrict__ ks, const uint8_t *in,
-                                                                 uint8_t *out, uint64_t n_blocks, int vec16) {
+__global__ __launch_bounds__(kThreads, kMainGroupsPerCU) void tdes_bitslice_kernel(const uint32_t *__restrict__ ks,
+                                                                                   const uint8_t *in, uint8_t *out,
+                                                                                   uint64_t n_tiles) {
+    const uint32_t lane = threadIdx.x % kLanes;
+    const uint64_t stride = (uint64_t)gridDim.x * kWaves;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
+    for (uint64_t tile = (uint64_t)blockIdx.x * kWaves + wave; tile < n_tiles; tile += stride) {
+        const uint64_t first = tile * kTileBlocks;
+        wave_tile<true>(ks, in + 8 * first, out + 8 * first, kTileBlocks, lane);
+    }
+}
+
+// Tiles first_tile.. of the message, any of them partial; 8-byte alignment suffices.
+__global__ __launch_bounds__(kThreads) void tdes_bitslice_tail_kernel(const uint32_t *__restrict__ ks,
+                                                                      const uint8_t *in, uint8_t *out,
+                                                                      uint64_t first_tile, uint64_t n_blocks) {
     const uint32_t lane = threadIdx.x % kLanes;
     const uint64_t tiles = (n_blocks + kTileBlocks - 1) / kTileBlocks;
-    const uint64_t stride = (uint64_t)gridDim.x * (kThreads / kLanes);
+    const uint64_t stride = (uint64_t)gridDim.x * kWaves;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
-    for (uint64_t tile = (uint64_t)blockIdx.x * (kThreads / kLanes) + wave; tile < tiles; tile += stride) {
+    for (uint64_t tile = first_tile + (uint64_t)blockIdx.x * kWaves + wave; tile < tiles; tile += stride) {
         const uint64_t first = tile * kTileBlocks;
         const uint64_t left = n_blocks - first;
         const uint32_t n_valid = left < kTileBlocks ? (uint32_t)left : kTileBlocks;
-        if (vec16 && n_valid == kTileBlocks)
-            wave_tile<true, kWaveKeys>(ks, in + 8 * first, out + 8 * first, n_valid, lane);
-        else
-            wave_tile<false, kWaveKeys>(ks, in + 8 * first, out + 8 * first, n_valid, lane);
+        wave_tile<false>(ks, in + 8 * first, out + 8 * first, n_valid, lane);
     }
+}
+
+uint32_t grid_for(uint64_t tiles) {
+    const uint64_t g = (tiles + kWaves - 1) / kWaves;
+    return (uint32_t)(g < kMaxGrid ? g : kMaxGrid);
 }
 
 }  // namespace
@@ -44,13 +66,20 @@ namespace tdes {
 
 hipError_t launch_bitslice(const uint32_t *ks, const uint8_t *in, uint8_t *out, uint64_t n_blocks,
                            hipStream_t stream) {
-    const uint64_t tiles = (n_blocks + kTileBlocks - 1) / kTileBlocks;
-    uint64_t grid = (tiles + kThreads / kLanes - 1) / (kThreads / kLanes);
-    if (grid > (1u << 20)) grid = 1u << 20;  // larger messages loop over tiles
-    const int vec16 = ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
-    hipLaunchKernelGGL(tdes_bitslice_kernel, dim3((unsigned)grid), dim3(kThreads), 0, stream, ks, in, out, n_blocks,
-                       vec16);
-    return hipGetLastError();
+    const bool vec16 = ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
+    const uint64_t whole = vec16 ? n_blocks / kTileBlocks : 0;
+    if (whole) {
+        hipLaunchKernelGGL(tdes_bitslice_kernel, dim3(grid_for(whole)), dim3(kThreads), 0, stream, ks, in, out, whole);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (whole * kTileBlocks < n_blocks) {
+        const uint64_t rest = (n_blocks - whole * kTileBlocks + kTileBlocks - 1) / kTileBlocks;
+        hipLaunchKernelGGL(tdes_bitslice_tail_kernel, dim3(grid_for(rest)), dim3(kThreads), 0, stream, ks, in, out,
+                           whole, n_blocks);
+        return hipGetLastError();
+    }
+    return hipSuccess;
 }
 
 }  // namespace tdes
