@@ -1,4 +1,4 @@
-"""Plain CPU reference for DES / Triple-DES (EDE) in ECB mode.
+"""Plain CPU reference for DES / Triple-DES (EDE) in ECB mode, and in the CBC and CTR modes.
 
 TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
 CPU-baseline leg may import this package; the product library never does.
@@ -8,7 +8,8 @@ Data Encryption Standard, bit by bit); this module only builds it with gcc and
 marshals arguments through ctypes.  See that file's header for the passages
 of the paper it follows (ECB independence of blocks: Abstract; the EDE order
 and its reversal for decryption: Section II.A; three keys giving 48 subkeys:
-Listing 1.1).
+Listing 1.1).  CBC and CTR go beyond the paper, which is ECB only; they follow
+the modes' definitions in NIST SP 800-38A (stated in the C file).
 """
 from __future__ import annotations
 
@@ -51,6 +52,10 @@ def _load():
         lib.oracle_des_cd_u64.restype = None
         lib.oracle_des_trace.argtypes = [u8p, u8p, ctypes.c_int, u8p]
         lib.oracle_des_trace.restype = None
+        lib.oracle_tdes_cbc.argtypes = [u8p, u8p, u8p, u8p, u8p, u8p, ctypes.c_uint64, ctypes.c_int]
+        lib.oracle_tdes_cbc.restype = ctypes.c_int
+        lib.oracle_tdes_ctr.argtypes = [u8p, u8p, u8p, u8p, u8p, u8p, ctypes.c_uint64]
+        lib.oracle_tdes_ctr.restype = ctypes.c_int
         lib.oracle_table.argtypes = [ctypes.c_char_p, u8p]
         lib.oracle_table.restype = ctypes.c_int
         _lib = lib
@@ -80,6 +85,35 @@ def tdes_ecb(k1, k2, k3, data, decrypt: bool = False, threads: int = 1) -> np.nd
                                  src.size // 8, int(bool(decrypt)), int(threads))
     if rc != 0:
         raise RuntimeError("oracle_tdes_ecb failed")
+    return out
+
+
+def _blocks(data) -> np.ndarray:
+    src = np.ascontiguousarray(np.frombuffer(bytes(data), dtype=np.uint8)
+                               if isinstance(data, (bytes, bytearray)) else np.asarray(data, dtype=np.uint8).reshape(-1))
+    if src.size % 8:
+        raise ValueError("the modes work on whole 8-byte blocks")
+    return src
+
+
+def tdes_cbc(k1, k2, k3, iv, data, decrypt: bool = False) -> np.ndarray:
+    """CBC with TDEA as the block cipher (SP 800-38A), sequential; returns a new uint8 array."""
+    src = _blocks(data)
+    out = np.empty_like(src)
+    a, b, c, v = _key(k1), _key(k2), _key(k3), _key(iv)
+    if _load().oracle_tdes_cbc(_ptr(a), _ptr(b), _ptr(c), _ptr(v), _ptr(src), _ptr(out), src.size // 8,
+                               int(bool(decrypt))) != 0:
+        raise RuntimeError("oracle_tdes_cbc failed")
+    return out
+
+
+def tdes_ctr(k1, k2, k3, iv, data) -> np.ndarray:
+    """CTR with TDEA as the block cipher (SP 800-38A): counter block j = IV + j mod 2^64, big-endian."""
+    src = _blocks(data)
+    out = np.empty_like(src)
+    a, b, c, v = _key(k1), _key(k2), _key(k3), _key(iv)
+    if _load().oracle_tdes_ctr(_ptr(a), _ptr(b), _ptr(c), _ptr(v), _ptr(src), _ptr(out), src.size // 8) != 0:
+        raise RuntimeError("oracle_tdes_ctr failed")
     return out
 
 

@@ -1,4 +1,4 @@
-"""OpenSSL's DES and DES-EDE3-ECB through ctypes: an outside library used only to pin the oracle.
+"""OpenSSL's DES, DES-EDE3-ECB and DES-EDE3-CBC through ctypes: an outside library used only to pin the oracle.
 
 It is used only if libcrypto can be loaded; the tests that use it skip otherwise.
 """
@@ -30,6 +30,7 @@ def _load():
             lib.EVP_CIPHER_CTX_new.restype = vp
             lib.EVP_CIPHER_CTX_free.argtypes = [vp]
             lib.EVP_des_ede3_ecb.restype = vp
+            lib.EVP_des_ede3_cbc.restype = vp
             lib.EVP_CipherInit_ex.argtypes = [vp, vp, vp, ctypes.c_char_p, ctypes.c_char_p, ctypes.c_int]
             lib.EVP_CIPHER_CTX_set_padding.argtypes = [vp, ctypes.c_int]
             lib.EVP_CipherUpdate.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int), vp, ctypes.c_int]
@@ -40,14 +41,13 @@ def _load():
     return _lib
 
 
-def tdes_ecb(k1: bytes, k2: bytes, k3: bytes, data, decrypt: bool = False) -> np.ndarray:
-    """OpenSSL EVP_des_ede3_ecb, no padding."""
+def _evp(cipher, key: bytes, iv, data, decrypt: bool) -> np.ndarray:
     lib = _load()
     src = np.ascontiguousarray(np.asarray(data, dtype=np.uint8).reshape(-1))
     out = np.empty(src.size + 16, dtype=np.uint8)
     ctx = lib.EVP_CIPHER_CTX_new()
     try:
-        if lib.EVP_CipherInit_ex(ctx, lib.EVP_des_ede3_ecb(), None, k1 + k2 + k3, None, 0 if decrypt else 1) != 1:
+        if lib.EVP_CipherInit_ex(ctx, cipher, None, key, iv, 0 if decrypt else 1) != 1:
             raise RuntimeError("EVP_CipherInit_ex failed")
         lib.EVP_CIPHER_CTX_set_padding(ctx, 0)
         outl = ctypes.c_int(0)
@@ -61,6 +61,16 @@ def tdes_ecb(k1: bytes, k2: bytes, k3: bytes, data, decrypt: bool = False) -> np
     finally:
         lib.EVP_CIPHER_CTX_free(ctx)
     return out[: src.size]
+
+
+def tdes_ecb(k1: bytes, k2: bytes, k3: bytes, data, decrypt: bool = False) -> np.ndarray:
+    """OpenSSL EVP_des_ede3_ecb, no padding."""
+    return _evp(_load().EVP_des_ede3_ecb(), k1 + k2 + k3, None, data, decrypt)
+
+
+def tdes_cbc(k1: bytes, k2: bytes, k3: bytes, iv: bytes, data, decrypt: bool = False) -> np.ndarray:
+    """OpenSSL EVP_des_ede3_cbc, no padding."""
+    return _evp(_load().EVP_des_ede3_cbc(), k1 + k2 + k3, bytes(iv), data, decrypt)
 
 
 def des_block(key: bytes, block: bytes, decrypt: bool = False) -> bytes:
