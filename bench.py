@@ -314,6 +314,20 @@ def main():
     for name, v in (("table", td.TDES_VARIANT_TABLE), ("bitslice", td.TDES_VARIANT_BITSLICE)):
         _, ms = time_plain(td, torch, sched, src, ct, pt, v, max(4, args.steps // 4), 2)
         variants[name] = round(N_BLOCKS * 8 / (sum(ms) / len(ms) / 1e3) / 1e9, 3)
+    # CTR and CBC decryption on the same core: kernel-only rate over the same message.
+    modes = {}
+    iv = bytes.fromhex("0123456789abcdef")
+    for name, fn in (("ctr", td.tdes_ctr_crypt), ("cbc_decrypt", td.tdes_cbc_decrypt)):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(6)]
+        for i, (a, b) in enumerate([(None, None)] * 2 + ev):
+            if a is not None:
+                a.record()
+            fn(sched, iv, src, ct, N_BLOCKS)
+            if b is not None:
+                b.record()
+        torch.cuda.synchronize()
+        ms = sum(a.elapsed_time(b) for a, b in ev) / len(ev)
+        modes[name] = {"gbs": round(N_BLOCKS * 8 / (ms / 1e3) / 1e9, 3), "kernel_ms": round(ms, 4)}
     # The timed run: the shipped default (TDES_VARIANT_AUTO = bitsliced).
     wall, launch_ms = time_plain(td, torch, sched, src, ct, pt, td.TDES_VARIANT_AUTO, args.steps, args.warmup)
     roundtrip_ok = bool(torch.equal(pt, src))
@@ -338,6 +352,7 @@ def main():
                      "hbm_frac": round(16 * N_BLOCKS / avg_launch_s / 1e9 / HBM_PEAK_GBS, 4),
                      "kernel_hash": kernel_hash()},
         "variants": variants,
+        "modes": modes,
         "roundtrip_ok": roundtrip_ok,
     }
     del ct, pt

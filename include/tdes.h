@@ -117,6 +117,32 @@ int tdes_ecb_decrypt(const void *dev_sched, const void *in, void *out, uint64_t 
 int tdes_ecb_run(const void *dev_sched, const void *in, void *out, uint64_t n_blocks, int direction,
                  int variant, void *stream);
 
+/* ---- block-parallel modes on the same round core ---- */
+
+/*
+ * The paper is ECB only (Abstract); these run its cipher, unchanged, in the
+ * two standard modes whose blocks are independent (NIST SP 800-38A, with
+ * Triple-DES EDE as the block cipher).  Blocks, schedules and alignment as in
+ * tdes_ecb_encrypt; n_blocks == 0 enqueues nothing.
+ *   iv: host, 8 bytes in the standard's byte order, read at the call.
+ *
+ * CTR: out[j] = in[j] XOR EDE(T_j), with counter block T_j = iv + j modulo
+ * 2^64 (the 8 bytes read as a big-endian integer).  The same call encrypts
+ * and decrypts.  in == out is allowed.
+ */
+int tdes_ctr_crypt(const void *dev_sched, const uint8_t iv[8], const void *in, void *out, uint64_t n_blocks,
+                   void *stream);
+
+/*
+ * CBC decryption: out[j] = EDE^-1(in[j]) XOR in[j-1], with in[-1] = iv.  Each
+ * output block reads the ciphertext block before it, so in and out must not
+ * overlap at all (in == out gives TDES_ERR_OVERLAP).  CBC encryption is a
+ * chain over the blocks and has no parallel form; it is not offered.
+ * Errors: as tdes_ecb_encrypt; TDES_ERR_NULL if iv is NULL.
+ */
+int tdes_cbc_decrypt(const void *dev_sched, const uint8_t iv[8], const void *in, void *out, uint64_t n_blocks,
+                     void *stream);
+
 /*
  * ECB over a message held in host memory (the paper's setting, Listing 1.1,
  * with the transfers overlapped instead of done once around the kernels):

@@ -24,6 +24,7 @@ __all__ = [
     "REQUEST_DTYPE", "COMPLETION_DTYPE", "tdes_server_create", "tdes_server_destroy", "tdes_server_now",
     "tdes_server_submit", "tdes_server_cancel", "tdes_server_poll", "tdes_server_wait_idle",
     "tdes_server_release", "tdes_server_stats", "tdes_server_run_trace", "tdes_ecb_host",
+    "tdes_ctr_crypt", "tdes_cbc_decrypt",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtdes.so")
@@ -94,6 +95,8 @@ def load_library():
         "tdes_ecb_encrypt": ([vp, vp, vp, u64, vp], i32),
         "tdes_ecb_decrypt": ([vp, vp, vp, u64, vp], i32),
         "tdes_ecb_run": ([vp, vp, vp, u64, i32, i32, vp], i32),
+        "tdes_ctr_crypt": ([vp, vp, vp, vp, u64, vp], i32),
+        "tdes_cbc_decrypt": ([vp, vp, vp, vp, u64, vp], i32),
         "tdes_status_str": ([i32], ctypes.c_char_p),
         "tdes_fill_splitmix64": ([vp, u64, u64, u64, vp], i32),
         "tdes_ctx_create": ([ctypes.POINTER(vp)], i32),
@@ -192,6 +195,27 @@ def tdes_ecb_run(dev_sched, src, dst, n_blocks=None, direction: int = TDES_ENCRY
     n = _nblocks(src, n_blocks)
     _check(load_library().tdes_ecb_run(_ptr(dev_sched), _ptr(src), _ptr(dst), n, int(direction), int(variant),
                                        _stream(stream, src)), "tdes_ecb_run")
+
+
+def _iv_buffer(iv):
+    b = bytes(iv) if iv is not None else None
+    if b is not None and len(b) != 8:
+        raise ValueError("an IV is 8 bytes")
+    return ctypes.create_string_buffer(b, 8) if b is not None else None
+
+
+def tdes_ctr_crypt(dev_sched, iv, src, dst, n_blocks=None, stream=None) -> None:
+    """CTR mode (encrypt or decrypt): dst = src XOR EDE(iv + j)."""
+    n = _nblocks(src, n_blocks)
+    _check(load_library().tdes_ctr_crypt(_ptr(dev_sched), _iv_buffer(iv), _ptr(src), _ptr(dst), n,
+                                         _stream(stream, src)), "tdes_ctr_crypt")
+
+
+def tdes_cbc_decrypt(dev_sched, iv, src, dst, n_blocks=None, stream=None) -> None:
+    """CBC decryption: dst[j] = EDE^-1(src[j]) XOR src[j-1], src[-1] = iv; src and dst must not overlap."""
+    n = _nblocks(src, n_blocks)
+    _check(load_library().tdes_cbc_decrypt(_ptr(dev_sched), _iv_buffer(iv), _ptr(src), _ptr(dst), n,
+                                           _stream(stream, src)), "tdes_cbc_decrypt")
 
 
 def tdes_ecb_encrypt(dev_sched, src, dst, n_blocks=None, stream=None) -> None:

@@ -203,45 +203,93 @@ __device__ __forceinline__ uint32_t opaque(uint32_t v) {
     return v;
 }
 
-// A wave tile: 2048 consecutive blocks starting at `tin`/`tout` (wave-uniform);
-// lane l holds blocks 128k + 2l and 128k + 2l + 1 (k = 0..15), so each access is
-// 16 bytes per lane over 1 KiB contiguous across the wave.  kFull: all 2048
-// blocks valid and both buffers 16-byte aligned.  Otherwise (n_valid < 2048,
-// or buffers only 8-byte aligned) each block is loaded and stored on its own,
-// at the same addresses, only if it is one of the first n_valid; lanes past
-// the end compute on zeros.
-template <bool kFull>
-__device__ __forceinline__ void wave_tile(const uint32_t *__restrict__ ks, const uint8_t *tin, uint8_t *tout,
-                                          uint32_t n_valid, uint32_t lane) {
+// Block-parallel modes built on the same core (NIST SP 800-38A, with TDEA as
+// the block cipher; the paper itself is ECB only):
+//   kEcb        out_j = E(in_j) or D(in_j), by the schedule;
+//   kCtr        out_j = in_j xor E(T_j), T_j = iv + j modulo 2^64 as a big-endian block;
+//   kCbcDecrypt out_j = D(in_j) xor in_{j-1}, in_{-1} = iv (never in place).
+// j is the block index in the message; `iv` holds the 8 IV bytes read as a
+// big-endian integer.
+enum class TileMode { kEcb, kCtr, kCbcDecrypt };
+
+// The standard's byte order as the two little-endian words a (bytes 0..3), b (bytes 4..7).
+__device__ __forceinline__ uint32_t be_hi_word(uint64_t v) { return __builtin_bswap32((uint32_t)(v >> 32)); }
+__device__ __forceinline__ uint32_t be_lo_word(uint64_t v) { return __builtin_bswap32((uint32_t)v); }
+
+// A wave tile: 2048 consecutive blocks starting at `tin`/`tout` (wave-uniform),
+// blocks first_block.. of the message; lane l holds blocks 128k + 2l and
+// 128k + 2l + 1 (k = 0..15), so each access is 16 bytes per lane over 1 KiB
+// contiguous across the wave.  kFull: all 2048 blocks valid and both buffers
+// 16-byte aligned.  Otherwise (n_valid < 2048, or buffers only 8-byte
+// aligned) each block is loaded and stored on its own, at the same
+// addresses, only if it is one of the first n_valid; lanes past the end
+// compute on zeros.
+template <TileMode kMode, bool kFull>
+__device__ __forceinline__ void mode_tile(const uint32_t *__restrict__ ks, const uint8_t *tin, uint8_t *tout,
+                                          uint32_t n_valid, uint32_t lane, uint64_t first_block, uint64_t iv) {
     uint32_t a[32], b[32];
     lane = opaque(lane);
+    if constexpr (kMode == TileMode::kCtr) {
+        const uint64_t t0 = iv + first_block;  // wraps modulo 2^64
 #pragma unroll
-    for (int k = 0; k < 16; k++) {
-        const uint8_t *p = tin + 1024 * k + 16 * lane;
-        if (kFull) {
-            const uint4 v = *reinterpret_cast<const uint4 *>(p);
-            a[2 * k] = v.x; b[2 * k] = v.y; a[2 * k + 1] = v.z; b[2 * k + 1] = v.w;
-        } else {
-            const uint32_t j = 128 * k + 2 * lane;
-            uint2 v0 = make_uint2(0, 0), v1 = make_uint2(0, 0);
-            if (j < n_valid) v0 = *reinterpret_cast<const uint2 *>(p);
-            if (j + 1 < n_valid) v1 = *reinterpret_cast<const uint2 *>(p + 8);
-            a[2 * k] = v0.x; b[2 * k] = v0.y; a[2 * k + 1] = v1.x; b[2 * k + 1] = v1.y;
+        for (int k = 0; k < 16; k++) {
+            const uint64_t t = t0 + (uint32_t)(128 * k + 2 * lane);
+            a[2 * k] = be_hi_word(t); b[2 * k] = be_lo_word(t);
+            a[2 * k + 1] = be_hi_word(t + 1); b[2 * k + 1] = be_lo_word(t + 1);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            const uint8_t *p = tin + 1024 * k + 16 * lane;
+            if (kFull) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(p);
+                a[2 * k] = v.x; b[2 * k] = v.y; a[2 * k + 1] = v.z; b[2 * k + 1] = v.w;
+            } else {
+                const uint32_t j = 128 * k + 2 * lane;
+                uint2 v0 = make_uint2(0, 0), v1 = make_uint2(0, 0);
+                if (j < n_valid) v0 = *reinterpret_cast<const uint2 *>(p);
+                if (j + 1 < n_valid) v1 = *reinterpret_cast<const uint2 *>(p + 8);
+                a[2 * k] = v0.x; b[2 * k] = v0.y; a[2 * k + 1] = v1.x; b[2 * k + 1] = v1.y;
+            }
         }
     }
     tdes_32_blocks<false>(a, b, ks);
     lane = opaque(lane);
 #pragma unroll
     for (int k = 0; k < 16; k++) {
-        uint8_t *p = tout + 1024 * k + 16 * lane;
+        const uint32_t j = 128 * k + 2 * lane;
+        const uint8_t *p = tin + 1024 * k + 16 * lane;
+        if constexpr (kMode == TileMode::kCtr) {  // the keystream meets the data
+            if (kFull) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(p);
+                a[2 * k] ^= v.x; b[2 * k] ^= v.y; a[2 * k + 1] ^= v.z; b[2 * k + 1] ^= v.w;
+            } else {
+                uint2 v0 = make_uint2(0, 0), v1 = make_uint2(0, 0);
+                if (j < n_valid) v0 = *reinterpret_cast<const uint2 *>(p);
+                if (j + 1 < n_valid) v1 = *reinterpret_cast<const uint2 *>(p + 8);
+                a[2 * k] ^= v0.x; b[2 * k] ^= v0.y; a[2 * k + 1] ^= v1.x; b[2 * k + 1] ^= v1.y;
+            }
+        } else if constexpr (kMode == TileMode::kCbcDecrypt) {  // XOR the preceding ciphertext blocks
+            uint2 v0 = make_uint2(be_hi_word(iv), be_lo_word(iv)), v1 = make_uint2(0, 0);
+            if (first_block + j != 0 && (kFull || j < n_valid)) v0 = *reinterpret_cast<const uint2 *>(p - 8);
+            if (kFull || j + 1 < n_valid) v1 = *reinterpret_cast<const uint2 *>(p);
+            a[2 * k] ^= v0.x; b[2 * k] ^= v0.y; a[2 * k + 1] ^= v1.x; b[2 * k + 1] ^= v1.y;
+        }
+        uint8_t *q = tout + 1024 * k + 16 * lane;
         if (kFull) {
-            *reinterpret_cast<uint4 *>(p) = make_uint4(a[2 * k], b[2 * k], a[2 * k + 1], b[2 * k + 1]);
+            *reinterpret_cast<uint4 *>(q) = make_uint4(a[2 * k], b[2 * k], a[2 * k + 1], b[2 * k + 1]);
         } else {
-            const uint32_t j = 128 * k + 2 * lane;
-            if (j < n_valid) *reinterpret_cast<uint2 *>(p) = make_uint2(a[2 * k], b[2 * k]);
-            if (j + 1 < n_valid) *reinterpret_cast<uint2 *>(p + 8) = make_uint2(a[2 * k + 1], b[2 * k + 1]);
+            if (j < n_valid) *reinterpret_cast<uint2 *>(q) = make_uint2(a[2 * k], b[2 * k]);
+            if (j + 1 < n_valid) *reinterpret_cast<uint2 *>(q + 8) = make_uint2(a[2 * k + 1], b[2 * k + 1]);
         }
     }
+}
+
+// ECB over a wave tile (see mode_tile).
+template <bool kFull>
+__device__ __forceinline__ void wave_tile(const uint32_t *__restrict__ ks, const uint8_t *tin, uint8_t *tout,
+                                          uint32_t n_valid, uint32_t lane) {
+    mode_tile<TileMode::kEcb, kFull>(ks, tin, tout, n_valid, lane, 0, 0);
 }
 
 // A lane slot: up to 32 consecutive blocks owned by this lane alone (its own

@@ -25,6 +25,12 @@ hipError_t launch_table(const uint32_t *ks, const uint8_t *in, uint8_t *out, uin
                         hipStream_t stream);
 hipError_t launch_bitslice(const uint32_t *ks, const uint8_t *in, uint8_t *out, uint64_t n_blocks,
                            hipStream_t stream);
+// Block-parallel modes (bitsliced): ks is the encryption half for CTR and the
+// decryption half for CBC decryption; iv is the 8 IV bytes read as a big-endian integer.
+hipError_t launch_ctr(const uint32_t *ks, const uint8_t *in, uint8_t *out, uint64_t n_blocks, uint64_t iv,
+                      hipStream_t stream);
+hipError_t launch_cbc_decrypt(const uint32_t *ks, const uint8_t *in, uint8_t *out, uint64_t n_blocks, uint64_t iv,
+                              hipStream_t stream);
 hipError_t launch_fill_splitmix64(uint64_t *dev, uint64_t n_words, uint64_t seed, uint64_t first,
                                   hipStream_t stream);
 

@@ -1,4 +1,5 @@
-// k_bitslice.hip -- Triple-DES ECB over one message, bitsliced variant (plain launch).
+// k_bitslice.hip -- Triple-DES over one message, bitsliced: ECB, and the CTR and
+// CBC-decrypt modes on the same core (plain launches).
 //
 // The paper maps one 64-bit block to one GPU thread and notes that the cipher
 // is almost entirely bit operations on integers (Abstract; Section IV).  Here a
@@ -27,22 +28,25 @@ constexpr int kWaves = kThreads / kLanes;
 constexpr int kMainGroupsPerCU = 4;      // 16 waves per CU: at most 128 VGPRs per lane
 constexpr uint64_t kMaxGrid = 1u << 20;
 
+template <TileMode kMode>
 __global__ __launch_bounds__(kThreads, kMainGroupsPerCU) void tdes_bitslice_kernel(const uint32_t *__restrict__ ks,
                                                                                    const uint8_t *in, uint8_t *out,
-                                                                                   uint64_t n_tiles) {
+                                                                                   uint64_t n_tiles, uint64_t iv) {
     const uint32_t lane = threadIdx.x % kLanes;
     const uint64_t stride = (uint64_t)gridDim.x * kWaves;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
     for (uint64_t tile = (uint64_t)blockIdx.x * kWaves + wave; tile < n_tiles; tile += stride) {
         const uint64_t first = tile * kTileBlocks;
-        wave_tile<true>(ks, in + 8 * first, out + 8 * first, kTileBlocks, lane);
+        mode_tile<kMode, true>(ks, in + 8 * first, out + 8 * first, kTileBlocks, lane, first, iv);
     }
 }
 
 // Tiles first_tile.. of the message, any of them partial; 8-byte alignment suffices.
+template <TileMode kMode>
 __global__ __launch_bounds__(kThreads) void tdes_bitslice_tail_kernel(const uint32_t *__restrict__ ks,
                                                                       const uint8_t *in, uint8_t *out,
-                                                                      uint64_t first_tile, uint64_t n_blocks) {
+                                                                      uint64_t first_tile, uint64_t n_blocks,
+                                                                      uint64_t iv) {
     const uint32_t lane = threadIdx.x % kLanes;
     const uint64_t tiles = (n_blocks + kTileBlocks - 1) / kTileBlocks;
     const uint64_t stride = (uint64_t)gridDim.x * kWaves;
@@ -51,7 +55,7 @@ __global__ __launch_bounds__(kThreads) void tdes_bitslice_tail_kernel(const uint
         const uint64_t first = tile * kTileBlocks;
         const uint64_t left = n_blocks - first;
         const uint32_t n_valid = left < kTileBlocks ? (uint32_t)left : kTileBlocks;
-        wave_tile<false>(ks, in + 8 * first, out + 8 * first, n_valid, lane);
+        mode_tile<kMode, false>(ks, in + 8 * first, out + 8 * first, n_valid, lane, first, iv);
     }
 }
 
@@ -60,26 +64,43 @@ uint32_t grid_for(uint64_t tiles) {
     return (uint32_t)(g < kMaxGrid ? g : kMaxGrid);
 }
 
+template <TileMode kMode>
+hipError_t launch(const uint32_t *ks, const uint8_t *in, uint8_t *out, uint64_t n_blocks, uint64_t iv,
+                  hipStream_t stream) {
+    const bool vec16 = ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
+    const uint64_t whole = vec16 ? n_blocks / kTileBlocks : 0;
+    if (whole) {
+        hipLaunchKernelGGL(tdes_bitslice_kernel<kMode>, dim3(grid_for(whole)), dim3(kThreads), 0, stream, ks, in, out,
+                           whole, iv);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (whole * kTileBlocks < n_blocks) {
+        const uint64_t rest = (n_blocks - whole * kTileBlocks + kTileBlocks - 1) / kTileBlocks;
+        hipLaunchKernelGGL(tdes_bitslice_tail_kernel<kMode>, dim3(grid_for(rest)), dim3(kThreads), 0, stream, ks, in,
+                           out, whole, n_blocks, iv);
+        return hipGetLastError();
+    }
+    return hipSuccess;
+}
+
 }  // namespace
 
 namespace tdes {
 
 hipError_t launch_bitslice(const uint32_t *ks, const uint8_t *in, uint8_t *out, uint64_t n_blocks,
                            hipStream_t stream) {
-    const bool vec16 = ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
-    const uint64_t whole = vec16 ? n_blocks / kTileBlocks : 0;
-    if (whole) {
-        hipLaunchKernelGGL(tdes_bitslice_kernel, dim3(grid_for(whole)), dim3(kThreads), 0, stream, ks, in, out, whole);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    if (whole * kTileBlocks < n_blocks) {
-        const uint64_t rest = (n_blocks - whole * kTileBlocks + kTileBlocks - 1) / kTileBlocks;
-        hipLaunchKernelGGL(tdes_bitslice_tail_kernel, dim3(grid_for(rest)), dim3(kThreads), 0, stream, ks, in, out,
-                           whole, n_blocks);
-        return hipGetLastError();
-    }
-    return hipSuccess;
+    return launch<TileMode::kEcb>(ks, in, out, n_blocks, 0, stream);
+}
+
+hipError_t launch_ctr(const uint32_t *ks, const uint8_t *in, uint8_t *out, uint64_t n_blocks, uint64_t iv,
+                      hipStream_t stream) {
+    return launch<TileMode::kCtr>(ks, in, out, n_blocks, iv, stream);
+}
+
+hipError_t launch_cbc_decrypt(const uint32_t *ks, const uint8_t *in, uint8_t *out, uint64_t n_blocks, uint64_t iv,
+                              hipStream_t stream) {
+    return launch<TileMode::kCbcDecrypt>(ks, in, out, n_blocks, iv, stream);
 }
 
 }  // namespace tdes
