@@ -116,7 +116,7 @@ def key_table(td, torch, inputs, seed, count, dev):
     host = np.empty(count * td.TDES_SCHED_BYTES, dtype=np.uint8)
     for i in range(count):
         k = keys[i]
-        host[i * 768:(i + 1) * 768] = td.tdes_expand_key(k[:8].tobytes(), k[8:16].tobytes(), k[16:].tobytes())
+        host[i * td.TDES_SCHED_BYTES:(i + 1) * td.TDES_SCHED_BYTES] = td.tdes_expand_key(k[:8].tobytes(), k[8:16].tobytes(), k[16:].tobytes())
     table = torch.empty(host.size, dtype=torch.uint8, device=dev)
     td.tdes_sched_upload(host, table)
     return table

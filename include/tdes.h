@@ -62,13 +62,14 @@ extern "C" {
 #define TDES_DECRYPT 1
 
 /* Size in bytes of one expanded schedule (both directions). */
-#define TDES_SCHED_BYTES 768
+#define TDES_SCHED_BYTES 1600
 
 /*
  * An expanded key triple: the 48 round subkeys (3 keys x 16 rounds) in the
- * order the rounds use them, once for encryption and once for decryption.
- * Plain old data; copy it to the device with tdes_sched_upload.  The layout
- * of the words is private to the library.
+ * order the rounds use them, once for encryption and once for decryption,
+ * each followed by key masks precomputed for the bitsliced kernels.  Plain
+ * old data; copy it to the device with tdes_sched_upload.  The layout of the
+ * words is private to the library.
  */
 typedef struct tdes_sched {
     uint32_t w[TDES_SCHED_BYTES / 4];
@@ -85,7 +86,7 @@ int tdes_expand_key(const uint8_t k1[8], const uint8_t k2[8], const uint8_t k3[8
                     tdes_sched *out);
 
 /*
- * Copy `count` schedules from host memory to a device table (count * 768 bytes,
+ * Copy `count` schedules from host memory to a device table (count * 1600 bytes,
  * 4-byte aligned).  The copy is ordered on `stream` and complete when the call
  * returns, so `host` may be reused at once.  count == 0 is a no-op.
  * Errors: TDES_ERR_NULL, TDES_ERR_ALIGN, TDES_ERR_SIZE, TDES_ERR_HIP.
@@ -170,7 +171,7 @@ typedef struct tdes_job {
     uint64_t in_off;     /* input of the message */
     uint64_t out_off;    /* output of the message */
     uint64_t n_blocks;   /* length in 8-byte blocks; 0 is allowed; at most 2^40 */
-    uint32_t sched_idx;  /* which schedule of the device table (768 bytes each) */
+    uint32_t sched_idx;  /* which schedule of the device table (TDES_SCHED_BYTES each) */
     uint32_t direction;  /* TDES_ENCRYPT or TDES_DECRYPT */
 } tdes_job;
 

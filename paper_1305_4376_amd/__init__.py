@@ -33,7 +33,7 @@ TDES_OK = 0
 TDES_ENCRYPT, TDES_DECRYPT = 0, 1
 TDES_CHECK_PARITY, TDES_REJECT_WEAK = 1, 2
 TDES_VARIANT_AUTO, TDES_VARIANT_TABLE, TDES_VARIANT_BITSLICE = 0, 1, 2
-TDES_SCHED_BYTES = 768
+TDES_SCHED_BYTES = 1600
 TDES_BATCH_NO_GRAPH, TDES_BATCH_PER_MESSAGE = 1, 2
 
 # struct tdes_job (include/tdes.h): 32 bytes.
@@ -167,7 +167,7 @@ def tdes_status_str(code: int) -> str:
 
 
 def tdes_expand_key(k1: bytes, k2: bytes, k3: bytes, flags: int = 0) -> np.ndarray:
-    """Host key expansion; returns the 768-byte schedule as a uint8 array."""
+    """Host key expansion; returns the TDES_SCHED_BYTES-byte schedule as a uint8 array."""
     keys = []
     for k in (k1, k2, k3):
         b = bytes(k)
@@ -180,11 +180,11 @@ def tdes_expand_key(k1: bytes, k2: bytes, k3: bytes, flags: int = 0) -> np.ndarr
 
 
 def tdes_sched_upload(host, dev_table, count: int | None = None, stream=None) -> None:
-    """Copy `count` host schedules (a uint8 array of count*768 bytes) to a device table."""
+    """Copy `count` host schedules (a uint8 array of count*TDES_SCHED_BYTES bytes) to a device table."""
     h = np.ascontiguousarray(np.asarray(host, dtype=np.uint8).reshape(-1))
     if count is None:
         if h.size % TDES_SCHED_BYTES:
-            raise ValueError("host schedules must be a multiple of 768 bytes")
+            raise ValueError(f"host schedules must be a multiple of {TDES_SCHED_BYTES} bytes")
         count = h.size // TDES_SCHED_BYTES
     _check(load_library().tdes_sched_upload(h.ctypes.data, int(count), _ptr(dev_table), _stream(stream, dev_table)),
            "tdes_sched_upload")

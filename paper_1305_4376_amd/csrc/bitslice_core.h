@@ -10,7 +10,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
-#include "des_spec.h"
+#include "bitslice_maps.h"
 
 namespace tdes_bs {
 
@@ -18,39 +18,6 @@ namespace tdes_bs {
 
 constexpr int kLanes = 64;
 constexpr int kTileBlocks = 32 * kLanes;     // blocks per wave tile
-
-// ---- compile-time plane maps ----
-
-// Transposed plane that holds block bit f (0-based, bit 0 = MSB of byte 0).
-// Half h (bytes 4h..4h+3) is loaded as a little-endian word whose bit i is
-// bit 7 - i % 8 of byte i / 8 of the half.
-constexpr int plane_of_bit(int f) { return 32 * (f / 32) + 8 * ((f % 32) / 8) + 7 - f % 8; }
-
-struct Maps {
-    int l0[32], r0[32];   // plane of IP output bit k (L0, R0)
-    int out_src[64];      // for plane p after FP: index into the preoutput R16 || L16 (0..63)
-    int e[48];            // R bit feeding S-box input 6s+j
-    int p_inv[32];        // f(R) bit receiving S-box output bit q
-};
-
-constexpr Maps make_maps() {
-    Maps m{};
-    for (int k = 0; k < 32; k++) {
-        m.l0[k] = plane_of_bit(tdes_spec::ip(k));
-        m.r0[k] = plane_of_bit(tdes_spec::ip(32 + k));
-    }
-    // FP = IP^-1: output bit ip(k) is preoutput bit k.
-    for (int k = 0; k < 64; k++) m.out_src[plane_of_bit(tdes_spec::ip(k))] = k;
-    for (int i = 0; i < 48; i++) m.e[i] = tdes_spec::expansion(i);
-    for (int i = 0; i < 32; i++) m.p_inv[tdes_spec::kP[i]] = i;
-    return m;
-}
-
-constexpr Maps kMaps = make_maps();
-
-// Key chunk of S-box s sits in schedule word s % 2 at byte ((8 + s % 2 - s) % 8) / 2,
-// its first bit at position 5 of the byte (the host layout of keysched.cpp).
-constexpr int key_pos(int s, int j) { return 8 * (((8 + s % 2 - s) % 8) / 2) + 5 - j; }
 
 // ---- bit transpose ----
 
@@ -153,12 +120,77 @@ __device__ __forceinline__ void des_stage(uint32_t (&x)[32], uint32_t (&y)[32], 
     }
 }
 
+// ---- rounds with folded key masks (one key for the whole wave) ----
+//
+// The scheme of bitslice_maps.h: the masks come from the direction's folded
+// words (32 output masks and 16 corrections per round, one scalar bit-field
+// extract each), so a round costs the S-box gates plus 32 three-way XORs and
+// 16 corrections, instead of 48 key XORs plus 32 XORs.
+
+template <int S>
+__device__ __forceinline__ void sbox_round_folded(uint32_t (&x)[32], const uint32_t (&y)[32], uint32_t out_in,
+                                                  uint32_t corr_in) {
+    const uint32_t ow = key_word<false>(out_in), cw = key_word<false>(corr_in);
+    uint32_t in[6];
+#pragma unroll
+    for (int j = 0; j < 6; j++) {
+        const int i = 6 * S + j, t = kUses.second_of[i];
+        in[j] = t < 0 ? y[kMaps.e[i]] : y[kMaps.e[i]] ^ key_mask(cw, t);
+    }
+    constexpr int p0 = kMaps.p_inv[4 * S + 0], p1 = kMaps.p_inv[4 * S + 1];
+    constexpr int p2 = kMaps.p_inv[4 * S + 2], p3 = kMaps.p_inv[4 * S + 3];
+    const uint32_t m0 = key_mask(ow, p0), m1 = key_mask(ow, p1), m2 = key_mask(ow, p2), m3 = key_mask(ow, p3);
+    if constexpr (S == 0) sbox0_m(in[0], in[1], in[2], in[3], in[4], in[5], x[p0], x[p1], x[p2], x[p3], m0, m1, m2, m3);
+    if constexpr (S == 1) sbox1_m(in[0], in[1], in[2], in[3], in[4], in[5], x[p0], x[p1], x[p2], x[p3], m0, m1, m2, m3);
+    if constexpr (S == 2) sbox2_m(in[0], in[1], in[2], in[3], in[4], in[5], x[p0], x[p1], x[p2], x[p3], m0, m1, m2, m3);
+    if constexpr (S == 3) sbox3_m(in[0], in[1], in[2], in[3], in[4], in[5], x[p0], x[p1], x[p2], x[p3], m0, m1, m2, m3);
+    if constexpr (S == 4) sbox4_m(in[0], in[1], in[2], in[3], in[4], in[5], x[p0], x[p1], x[p2], x[p3], m0, m1, m2, m3);
+    if constexpr (S == 5) sbox5_m(in[0], in[1], in[2], in[3], in[4], in[5], x[p0], x[p1], x[p2], x[p3], m0, m1, m2, m3);
+    if constexpr (S == 6) sbox6_m(in[0], in[1], in[2], in[3], in[4], in[5], x[p0], x[p1], x[p2], x[p3], m0, m1, m2, m3);
+    if constexpr (S == 7) sbox7_m(in[0], in[1], in[2], in[3], in[4], in[5], x[p0], x[p1], x[p2], x[p3], m0, m1, m2, m3);
+}
+
+// x ^= f(y) for one round, with its output-fold and correction words.
+__device__ __forceinline__ void feistel_folded(uint32_t (&x)[32], const uint32_t (&y)[32], uint32_t ow, uint32_t cw) {
+    sbox_round_folded<0>(x, y, ow, cw);
+    sbox_round_folded<1>(x, y, ow, cw);
+    sbox_round_folded<2>(x, y, ow, cw);
+    sbox_round_folded<3>(x, y, ow, cw);
+    sbox_round_folded<4>(x, y, ow, cw);
+    sbox_round_folded<5>(x, y, ow, cw);
+    sbox_round_folded<6>(x, y, ow, cw);
+    sbox_round_folded<7>(x, y, ow, cw);
+}
+
+// h[q] ^= bit q of w, for every plane q.
+__device__ __forceinline__ void fold_fix(uint32_t (&h)[32], uint32_t w_in) {
+    const uint32_t w = key_word<false>(w_in);
+#pragma unroll
+    for (int q = 0; q < 32; q++) h[q] ^= key_mask(w, q);
+}
+
+// Stage `stage` (0..2) of EDE with folded masks: x holds L0 and y holds R0 on
+// entry, L16 and R16 on exit (both without folded keys).  fold: the direction's
+// folded words.
+__device__ __forceinline__ void des_stage_folded(uint32_t (&x)[32], uint32_t (&y)[32],
+                                                 const uint32_t *__restrict__ fold, int stage) {
+    fold_fix(y, fold[kFoldPre + stage]);
+    const uint32_t *ow = fold + kFoldOut + 16 * stage, *cw = fold + kFoldCorr + 16 * stage;
+#pragma unroll 1
+    for (int r = 0; r < 16; r += 2) {
+        feistel_folded(x, y, ow[r], cw[r]);
+        feistel_folded(y, x, ow[r + 1], cw[r + 1]);
+    }
+    fold_fix(x, fold[kFoldPost + stage]);
+}
+
 // ---- kernel ----
 
 // The whole EDE (or its inverse, by the schedule) on 32 blocks held as two
 // arrays of little-endian words: a[j] = bytes 0..3 and b[j] = bytes 4..7 of
-// block j.  ks: the 96 schedule words of one direction, wave-uniform
-// (kLaneKeys = false) or per lane (kLaneKeys = true).
+// block j.  ks: one direction's schedule words, wave-uniform (kLaneKeys =
+// false: the folded words are used) or per lane (kLaneKeys = true: the round
+// words, one key XOR per S-box input).
 template <bool kLaneKeys>
 __device__ __forceinline__ void tdes_32_blocks(uint32_t (&a)[32], uint32_t (&b)[32], const uint32_t *__restrict__ ks) {
     transpose32(a);
@@ -174,7 +206,10 @@ __device__ __forceinline__ void tdes_32_blocks(uint32_t (&a)[32], uint32_t (&b)[
     // swap.  One loop runs all three, so the round code exists once.
 #pragma unroll 1
     for (int stage = 0; stage < 3; stage++) {
-        des_stage<kLaneKeys>(l, r, ks + 32 * stage);
+        if constexpr (kLaneKeys)
+            des_stage<true>(l, r, ks + 32 * stage);
+        else
+            des_stage_folded(l, r, ks + kFoldBase, stage);
         if (stage < 2) {
 #pragma unroll
             for (int k = 0; k < 32; k++) {

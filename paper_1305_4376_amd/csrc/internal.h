@@ -7,10 +7,14 @@
 
 namespace tdes {
 
-// Words of a schedule: encryption rounds first, then decryption rounds.
-// Round r of a direction uses words 2r (boxes 1,7,5,3 chunks) and 2r+1.
+// Words of a schedule: the encryption block, then the decryption block, each
+// kDirWords long: its kRoundWords round words (round r uses words 2r, the key
+// chunks of boxes 1,7,5,3, and 2r+1) followed by the folded key words of the
+// bitsliced kernels (bitslice_maps.h).
 constexpr int kRounds = 48;
-constexpr int kDirWords = 2 * kRounds;
+constexpr int kRoundWords = 2 * kRounds;
+constexpr int kDirWords = 200;
+static_assert(kRoundWords + 102 <= kDirWords && 2 * kDirWords * 4 == TDES_SCHED_BYTES, "schedule layout");
 
 // Per-device properties the launchers need (cached on first use).
 struct DeviceInfo {

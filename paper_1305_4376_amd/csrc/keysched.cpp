@@ -15,12 +15,16 @@
 //   word B = c1 | c7 << 8 | c5 << 16 | c3 << 24   (matches rotl(R, 9))
 #include <string.h>
 
+#include "bitslice_maps.h"
 #include "des_spec.h"
 #include "internal.h"
 
 namespace {
 
 using namespace tdes_spec;
+
+static_assert(tdes_bs::kFoldBase == tdes::kRoundWords && tdes::kRoundWords + tdes_bs::kFoldWords <= tdes::kDirWords,
+              "folded words follow the round words of each direction");
 
 uint64_t load_be64(const uint8_t k[8]) {
     uint64_t v = 0;
@@ -55,6 +59,37 @@ void pack_round(uint64_t sub, uint32_t *w) {
     for (int b = 0; b < 8; b++) c[b] = (uint32_t)(sub >> (42 - 6 * b)) & 63u;
     w[0] = c[0] | c[6] << 8 | c[4] << 16 | c[2] << 24;
     w[1] = c[1] | c[7] << 8 | c[5] << 16 | c[3] << 24;
+}
+
+// Key bit at E position i (0..47) of a 48-bit subkey (subkey bit 0 in bit 47).
+inline uint32_t key_bit(uint64_t sub, int i) { return (uint32_t)(sub >> (47 - i)) & 1u; }
+
+// The folded key words of one direction (layout in bitslice_maps.h) from its 48
+// subkeys in round order.
+void fold_words(const uint64_t sub[48], uint32_t *w) {
+    using tdes_bs::kMaps;
+    using tdes_bs::kUses;
+    for (int r = 0; r < 48; r++) {
+        const int i = r % 16;
+        const uint64_t diff = (i > 0 ? sub[r - 1] : 0) ^ (i < 15 ? sub[r + 1] : 0);
+        uint32_t out = 0, corr = 0;
+        for (int q = 0; q < 32; q++) out |= key_bit(diff, kUses.first[q]) << q;
+        for (int t = 0; t < 16; t++) {
+            const int pos = kUses.second_pos[t];
+            corr |= (key_bit(sub[r], kUses.first[kMaps.e[pos]]) ^ key_bit(sub[r], pos)) << t;
+        }
+        w[tdes_bs::kFoldOut + r] = out;
+        w[tdes_bs::kFoldCorr + r] = corr;
+    }
+    for (int st = 0; st < 3; st++) {
+        uint32_t pre = 0, post = 0;
+        for (int q = 0; q < 32; q++) {
+            pre |= key_bit(sub[16 * st], kUses.first[q]) << q;
+            post |= key_bit(sub[16 * st + 15], kUses.first[q]) << q;
+        }
+        w[tdes_bs::kFoldPre + st] = pre;
+        w[tdes_bs::kFoldPost + st] = post;
+    }
 }
 
 // C0 and D0 of a key, for the weak-key test.
@@ -102,16 +137,22 @@ extern "C" int tdes_expand_key(const uint8_t k1[8], const uint8_t k2[8], const u
     uint64_t sub[3][16];
     for (int i = 0; i < 3; i++) des_subkeys(keys[i], sub[i]);
 
+    // The 48 subkeys of each direction in the order its rounds use them.
+    uint64_t order[2][48];
+    for (int r = 0; r < 16; r++) {
+        order[0][r] = sub[0][r];             // E under K1
+        order[0][16 + r] = sub[1][15 - r];   // D under K2
+        order[0][32 + r] = sub[2][r];        // E under K3
+        order[1][r] = sub[2][15 - r];        // D under K3
+        order[1][16 + r] = sub[1][r];        // E under K2
+        order[1][32 + r] = sub[0][15 - r];   // D under K1
+    }
     tdes_sched s;
     memset(&s, 0, sizeof s);
-    uint32_t *enc = s.w, *dec = s.w + tdes::kDirWords;
-    for (int r = 0; r < 16; r++) {
-        pack_round(sub[0][r], enc + 2 * r);             // E under K1
-        pack_round(sub[1][15 - r], enc + 2 * (16 + r));  // D under K2
-        pack_round(sub[2][r], enc + 2 * (32 + r));      // E under K3
-        pack_round(sub[2][15 - r], dec + 2 * r);        // D under K3
-        pack_round(sub[1][r], dec + 2 * (16 + r));      // E under K2
-        pack_round(sub[0][15 - r], dec + 2 * (32 + r));  // D under K1
+    for (int d = 0; d < 2; d++) {
+        uint32_t *w = s.w + d * tdes::kDirWords;
+        for (int r = 0; r < 48; r++) pack_round(order[d][r], w + 2 * r);
+        fold_words(order[d], w + tdes::kRoundWords);
     }
     *out = s;
     return TDES_OK;

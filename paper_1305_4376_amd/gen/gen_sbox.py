@@ -157,6 +157,7 @@ def emit(circuits: dict[int, Circuit], boxes) -> str:
     out = ["// Generated by gen/gen_sbox.py from gen/sbox_circuits.txt; do not edit.",
            "// sbox<b>(x0..x5, o0..o3): o_j ^= output bit j of S-box b+1 for inputs x0..x5",
            "// (x0 = first input bit, o0 = first output bit), 32 lanes of bits at once.",
+           "// sbox<b>_m(x0..x5, o0..o3, m0..m3): o_j ^= output bit j ^ m_j (m_j a key mask, 0 or ~0).",
            "// Each gate is one v_bitop3_b32 (truth table bit 4a+2b+c).", ""]
     total = 0
     for b in range(8):
@@ -193,6 +194,15 @@ def emit(circuits: dict[int, Circuit], boxes) -> str:
             if j in folded:
                 continue
             out.append(f"    o{j} = ~(o{j} ^ n{o});" if pol[j] else f"    o{j} ^= n{o};")
+        out.append("}")
+        out.append("")
+        # masked variant: every output is a three-way XOR (Feistel plane, S-box bit, key mask)
+        out.append(f"__device__ __forceinline__ void sbox{b}_m({head}, uint32_t m0, uint32_t m1, uint32_t m2, "
+                   f"uint32_t m3) {{")
+        for node, a, bb, cc, lut in c.gates:
+            out.append(f"    const uint32_t n{node} = __builtin_amdgcn_bitop3_b32(n{a}, n{bb}, n{cc}, 0x{lut:02X});")
+        for j, o in enumerate(c.outs):
+            out.append(f"    o{j} = __builtin_amdgcn_bitop3_b32(o{j}, n{o}, m{j}, 0x{0x69 if pol[j] else 0x96:02X});")
         out.append("}")
         out.append("")
     out.append(f"// Total over the eight boxes: {total} operations; average {total / 8:.2f}.")

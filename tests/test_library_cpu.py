@@ -44,6 +44,9 @@ def test_status_strings():
     assert td.tdes_status_str(-99) == "unknown status"
 
 
+DIR_WORDS = td.TDES_SCHED_BYTES // 8  # each direction's block of the schedule, in words
+
+
 def _decode(sched: np.ndarray):
     """The schedule's private round layout, back to 48-bit subkeys (two directions x 48 rounds)."""
     w = sched.view("<u4")
@@ -51,7 +54,7 @@ def _decode(sched: np.ndarray):
     for d in range(2):
         rounds = []
         for r in range(48):
-            a, b = int(w[96 * d + 2 * r]), int(w[96 * d + 2 * r + 1])
+            a, b = int(w[DIR_WORDS * d + 2 * r]), int(w[DIR_WORDS * d + 2 * r + 1])
             c = [0] * 8
             c[0], c[6], c[4], c[2] = (a & 63), (a >> 8) & 63, (a >> 16) & 63, (a >> 24) & 63
             c[1], c[7], c[5], c[3] = (b & 63), (b >> 8) & 63, (b >> 16) & 63, (b >> 24) & 63
@@ -98,7 +101,7 @@ def test_expand_key_flags():
 
 def test_expand_key_null_arguments():
     lib = td.load_library()
-    out = np.zeros(768, np.uint8)
+    out = np.zeros(td.TDES_SCHED_BYTES, np.uint8)
     k = ctypes.create_string_buffer(b"\x01" * 8, 8)
     assert lib.tdes_expand_key(None, k, k, 0, out.ctypes.data) == -1
     assert lib.tdes_expand_key(k, k, k, 0, None) == -1
@@ -176,3 +179,38 @@ def test_host_path_argument_errors():
     assert lib.tdes_ecb_host(s, a, b, 8, 5, 1, None) == -7
     assert lib.tdes_ecb_host(s, a, b, 8, 0, 0, None) == -4
     assert lib.tdes_ecb_host(s, a, a + 8, 8, 0, 4, None) == -3
+
+
+def _oracle_first_and_second_uses():
+    """From the oracle's E table: the first E position reading each R bit, and the second uses in order."""
+    e = [x - 1 for x in oracle.table("E")]
+    first, second = {}, []
+    for i, q in enumerate(e):
+        if q in first:
+            second.append(i)
+        else:
+            first[q] = i
+    return e, first, second
+
+
+@pytest.mark.parametrize("keying", [3, 2, 1])
+def test_folded_key_words_match_oracle_subkeys(keying):
+    """The bitsliced kernels' folded mask words, rebuilt here from the oracle's subkeys and E table."""
+    e, first, second = _oracle_first_and_second_uses()
+    assert len(second) == 16
+    bit = lambda k, i: (k >> (47 - i)) & 1
+    for seed in range(4):
+        k1, k2, k3 = inputs.key_triple(0x720 + seed, keying)
+        s1, s2, s3 = oracle.des_subkeys(k1), oracle.des_subkeys(k2), oracle.des_subkeys(k3)
+        w = td.tdes_expand_key(k1, k2, k3).view("<u4")
+        for d, order in enumerate((s1 + s2[::-1] + s3, s3[::-1] + s2 + s1[::-1])):
+            fold = w[DIR_WORDS * d + 96: DIR_WORDS * d + 96 + 102]
+            for r in range(48):
+                i = r % 16
+                diff = (order[r - 1] if i > 0 else 0) ^ (order[r + 1] if i < 15 else 0)
+                assert int(fold[r]) == sum(bit(diff, first[q]) << q for q in range(32)), (d, r)
+                corr = sum((bit(order[r], first[e[p]]) ^ bit(order[r], p)) << t for t, p in enumerate(second))
+                assert int(fold[48 + r]) == corr, (d, r)
+            for st in range(3):
+                assert int(fold[96 + st]) == sum(bit(order[16 * st], first[q]) << q for q in range(32))
+                assert int(fold[99 + st]) == sum(bit(order[16 * st + 15], first[q]) << q for q in range(32))
