@@ -1,12 +1,14 @@
 // bitslice_core.h -- the bitsliced Triple-DES round core shared by the plain and batched kernels.
 //
 // A lane holds 32 blocks as 64 bit planes: plane f is a 32-bit word whose bit j
-// is bit f of the lane's block j.  IP, E, P and IP^-1 are renamings of planes;
-// the subkey XOR is one XOR per S-box input plane with a mask (0 or ~0) taken
-// from the schedule word (a scalar register when the key is the same for the
-// whole wave, a vector register when lanes use different keys); each S-box is
-// a circuit of 3-input lookup gates (sbox_circuits.inc).  Blocks become planes
-// by an in-register 32x32 bit transpose of each 4-byte half of the 32 blocks.
+// is bit f of the lane's block j.  IP, E, P and IP^-1 are renamings of planes
+// (bitslice_maps.h); each S-box is a circuit of 3-input lookup gates
+// (sbox_circuits.inc).  Key bits enter as masks (0 or ~0): when the key is the
+// same for the whole wave, folded into the halves between rounds, from words
+// the host precomputes (scalar registers); when lanes have different keys, one
+// XOR per S-box input from the round words (vector registers).  Blocks become
+// planes by an in-register 32x32 bit transpose of each 4-byte half of the 32
+// blocks.
 #pragma once
 #include <hip/hip_runtime.h>
 

@@ -231,7 +231,9 @@ def main():
             if c is None:
                 continue
             c.polarities(boxes[b])  # raises if wrong
-            if b not in circuits or c.cost() < circuits[b].cost():
+            # Fewest gates first (the folded rounds pay one three-way XOR per output anyway),
+            # then the cost with the output XORs of the per-lane-key rounds.
+            if b not in circuits or (len(c.gates), c.cost()) < (len(circuits[b].gates), circuits[b].cost()):
                 circuits[b] = c
                 print(f"S{b + 1}: {len(c.gates)} gates, cost {c.cost()}", file=sys.stderr)
         save_store(circuits, args.store)

@@ -26,11 +26,13 @@
  *      v = 0 and B = t where v = 1; or a bi-decomposition on two nodes,
  *      t = F(a, b, X), where on every cell of (a, b) t is constant or equal to
  *      X or its complement, the polarities picked to make X cheapest.
- * The four outputs are realized in a random order, sharing all nodes; many
- * random restarts run and the cheapest circuit is kept, where the cost is the
- * gate count plus one for each output whose final gate cannot also absorb the
- * XOR into the Feistel half (a final gate with three operands, or one that is
- * shared).
+ * The four outputs are realized in a random order, sharing all nodes (with
+ * WIDTH > 1, each output is realized WIDTH times from the same circuit and
+ * the attempt that adds the fewest gates is kept); many
+ * random restarts run and the circuit with the fewest gates is kept, ties
+ * broken by the cost: the gate count plus one for each output whose final gate
+ * cannot also absorb the XOR into the Feistel half (a final gate with three
+ * operands, or one that is shared).
  */
 #include <stdint.h>
 #include <stdio.h>
@@ -379,9 +381,10 @@ static void prune(circuit_t *C, int outs[4]) {
 
 int main(int argc, char **argv) {
     if (argc < 66) {
-        fprintf(stderr, "usage: sbox_search SEED TRIALS BUDGET2 s0 .. s63\n");
+        fprintf(stderr, "usage: sbox_search SEED TRIALS BUDGET2 s0 .. s63 [WIDTH]\n");
         return 2;
     }
+    const int width = argc > 67 ? atoi(argv[67]) : 1;  /* attempts per output, best kept */
     rng_state ^= strtoull(argv[1], NULL, 0);
     int trials = atoi(argv[2]);
     int budget2 = atoi(argv[3]);
@@ -394,6 +397,7 @@ int main(int argc, char **argv) {
             if ((sbox[p] >> (3 - j)) & 1) target[j] |= 1ull << p;
     }
     circuit_t best;
+    best.n = 6;
     int best_cost = 1 << 30, best_outs[4] = {0};
     for (int trial = 0; trial < trials; trial++) {
         g_allow_bidec = (int)(rnd() % 3 == 0);
@@ -406,9 +410,18 @@ int main(int argc, char **argv) {
         int outs[4], ok = 1;
         for (int q = 0; q < 4 && ok; q++) {
             int j = order[q];
-            int k = realize_top(&C, target[j], ~0ull, budget2);
-            if (k < 0) { ok = 0; break; }
-            outs[j] = k;
+            /* best of `width` attempts for this output, each from the same shared circuit */
+            circuit_t keep;
+            int keep_k = -1;
+            for (int w = 0; w < width; w++) {
+                circuit_t A = C;
+                int k = realize_top(&A, target[j], ~0ull, budget2);
+                if (k < 0) continue;
+                if (keep_k < 0 || A.n < keep.n) { keep = A; keep_k = k; }
+            }
+            if (keep_k < 0) { ok = 0; break; }
+            C = keep;
+            outs[j] = keep_k;
         }
         if (!ok) continue;
         prune(&C, outs);
@@ -420,7 +433,9 @@ int main(int argc, char **argv) {
             for (int i = 0; i < j; i++) if (outs[i] == o) extra++;
         }
         int cost = gates + extra;
-        if (cost < best_cost) {
+        /* Gates first: the kernels' folded rounds XOR every output with a key mask in a
+           three-way gate anyway; the absorbable outputs only help the per-lane-key rounds. */
+        if (gates < best.n - 6 || (gates == best.n - 6 && cost < best_cost) || best_cost >= (1 << 30)) {
             best_cost = cost; best = C; memcpy(best_outs, outs, sizeof outs);
             fprintf(stderr, "trial %d: gates %d cost %d\n", trial, gates, cost);
         }

@@ -168,6 +168,28 @@ def test_c2_one_gib_sampled(variant):
     torch.cuda.empty_cache()
 
 
+def test_c2_one_gib_every_block():
+    """The 1 GiB message encrypted by the shipped kernel, compared with the oracle on every one of its
+    2^27 blocks (the oracle on the host's cores, in 32 MiB pieces as the GPU output is copied back)."""
+    n = 1 << 27
+    seed = inputs.DATA_SEED_BASE + 1
+    keys = inputs.key_triple(inputs.KEY_SEED_BASE + 1)
+    sched = _gpu.device_sched(*keys)
+    src = _gpu.device_message(seed, n)
+    ct = torch.empty_like(src)
+    print(f"[parity] C2 1 GiB every block, oracle on {_gpu.ORACLE_THREADS} threads", flush=True)
+    td.tdes_ecb_encrypt(sched, src, ct)
+    torch.cuda.synchronize()
+    piece = 1 << 22
+    for first in range(0, n, piece):
+        host_in = inputs.message(seed, piece, first_block=first)
+        want = _gpu.oracle_on_blocks(keys, host_in, False)
+        got = ct[8 * first: 8 * (first + piece)].cpu().numpy()
+        assert np.array_equal(got, want), f"blocks {first}..{first + piece}"
+    del ct, src
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("pinned", [True, False])
 def test_host_resident_message(pinned):
     """A message in host memory, copies and kernels pipelined in chunks (a ragged last chunk)."""
