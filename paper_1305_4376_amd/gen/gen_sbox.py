@@ -1,6 +1,7 @@
 """Generate the bitsliced kernel's S-box circuits (csrc/sbox_circuits.inc).
 
-    python -m paper_1305_4376_amd.gen.gen_sbox [--search TRIALS] [--budget N] [--seeds K]
+    python -m paper_1305_4376_amd.gen.gen_sbox [--search TRIALS] [--budget N] [--seeds K] [--width W]
+                                               [--polish ITERATIONS]
 
 Each of the eight DES S-boxes (read from csrc/des_spec.h, the table the other
 kernel uses too) becomes a function of six bit planes that XORs its four
@@ -11,8 +12,10 @@ whose bit (4a + 2b + c) is the output for operand bits a, b, c.
 The circuits come from sbox_search.c (a randomized decomposition search
 written for this purpose; see that file).  The chosen ones are stored in
 sbox_circuits.txt; with --search the search runs again and a circuit replaces
-the stored one only if it is cheaper.  Every circuit is checked on all 64
-inputs before any code is written.
+the stored one only if it has fewer gates (then a lower cost).  --polish runs
+two local improvers on the stored circuits: sbox_cgp.c (evolution with
+resubstitution) and sbox_resyn.c (resynthesis of fanout-free cones).  Every
+circuit is checked on all 64 inputs before any code is written.
 """
 from __future__ import annotations
 
@@ -30,6 +33,8 @@ SPEC = os.path.join(PKG, "csrc", "des_spec.h")
 OUT_INC = os.path.join(PKG, "csrc", "sbox_circuits.inc")
 STORE = os.path.join(HERE, "sbox_circuits.txt")
 SEARCH_SRC = os.path.join(HERE, "sbox_search.c")
+CGP_SRC = os.path.join(HERE, "sbox_cgp.c")
+RESYN_SRC = os.path.join(HERE, "sbox_resyn.c")
 
 MASK64 = (1 << 64) - 1
 
@@ -139,16 +144,25 @@ def save_store(circuits: dict[int, Circuit], path: str = STORE):
             f.write(f"box {b + 1}\n{circuits[b].dump()}\n")
 
 
-def build_search() -> str:
-    exe = os.path.join(tempfile.gettempdir(), "tdes_sbox_search")
-    subprocess.check_call(["gcc", "-O2", "-o", exe, SEARCH_SRC])
+def build_tool(src: str) -> str:
+    exe = os.path.join(tempfile.gettempdir(), "tdes_" + os.path.splitext(os.path.basename(src))[0])
+    subprocess.check_call(["gcc", "-O2", "-o", exe, src])
     return exe
 
 
-def run_search(exe, tab, seed, trials, budget) -> Circuit | None:
-    res = subprocess.run([exe, str(seed), str(trials), str(budget), *map(str, tab)],
+def run_search(exe, tab, seed, trials, budget, width=1) -> Circuit | None:
+    res = subprocess.run([exe, str(seed), str(trials), str(budget)] + [str(v) for v in tab] + [str(width)],
                          stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, text=True)
     if res.returncode != 0:
+        return None
+    return Circuit.parse(res.stdout.split("\n", 1)[1])
+
+
+def run_polish(exe, args, tab, circuit: Circuit) -> Circuit | None:
+    """Feed a stored circuit to a local improver; return its output circuit (or None)."""
+    res = subprocess.run([exe] + [str(a) for a in args] + [str(v) for v in tab], input=circuit.dump(),
+                         stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, text=True)
+    if res.returncode != 0 or "\n" not in res.stdout:
         return None
     return Circuit.parse(res.stdout.split("\n", 1)[1])
 
@@ -214,28 +228,47 @@ def main():
     ap.add_argument("--search", type=int, default=0, help="random restarts per seed (0: use stored circuits)")
     ap.add_argument("--budget", type=int, default=200000)
     ap.add_argument("--seeds", type=int, default=8)
+    ap.add_argument("--width", type=int, default=1, help="search: attempts per output, best kept")
+    ap.add_argument("--polish", type=int, default=0, help="iterations of the local improvers (0: none)")
     ap.add_argument("--boxes", default="1,2,3,4,5,6,7,8")
     ap.add_argument("--store", default=STORE, help="circuit store to read and update")
     ap.add_argument("--out", default=OUT_INC, help="generated HIP include")
     args = ap.parse_args()
     boxes = sbox_tables()
     circuits = load_store(args.store)
+    todo = [int(b) - 1 for b in args.boxes.split(",")]
+
+    def accept(b, c, how):
+        if c is None:
+            return
+        c.polarities(boxes[b])  # raises if wrong
+        # Fewest gates first (the folded rounds pay one three-way XOR per output anyway),
+        # then the cost with the output XORs of the per-lane-key rounds.
+        if b not in circuits or (len(c.gates), c.cost()) < (len(circuits[b].gates), circuits[b].cost()):
+            circuits[b] = c
+            print(f"S{b + 1}: {len(c.gates)} gates, cost {c.cost()} ({how})", file=sys.stderr)
+
+    workers = os.cpu_count() or 4
     if args.search:
-        exe = build_search()
-        todo = [int(b) - 1 for b in args.boxes.split(",")]
+        exe = build_tool(SEARCH_SRC)
         jobs = [(b, s) for b in todo for s in range(args.seeds)]
-        with ThreadPoolExecutor(max_workers=os.cpu_count() or 4) as pool:
+        with ThreadPoolExecutor(max_workers=workers) as pool:
             results = list(pool.map(lambda bs: (bs[0], run_search(exe, boxes[bs[0]], 1000 * bs[0] + bs[1] + 1,
-                                                                   args.search, args.budget)), jobs))
+                                                                   args.search, args.budget, args.width)), jobs))
         for b, c in results:
-            if c is None:
-                continue
-            c.polarities(boxes[b])  # raises if wrong
-            # Fewest gates first (the folded rounds pay one three-way XOR per output anyway),
-            # then the cost with the output XORs of the per-lane-key rounds.
-            if b not in circuits or (len(c.gates), c.cost()) < (len(circuits[b].gates), circuits[b].cost()):
-                circuits[b] = c
-                print(f"S{b + 1}: {len(c.gates)} gates, cost {c.cost()}", file=sys.stderr)
+            accept(b, c, "search")
+    if args.polish:
+        cgp, resyn = build_tool(CGP_SRC), build_tool(RESYN_SRC)
+        jobs = [(b, s) for b in todo if b in circuits for s in range(args.seeds)]
+        with ThreadPoolExecutor(max_workers=workers) as pool:
+            results = list(pool.map(lambda bs: (bs[0], run_polish(cgp, [bs[1] + 1, args.polish, 8], boxes[bs[0]],
+                                                                  circuits[bs[0]])), jobs))
+        for b, c in results:
+            accept(b, c, "evolution")
+        for b in todo:
+            if b in circuits:
+                accept(b, run_polish(resyn, [1, 8], boxes[b], circuits[b]), "cone resynthesis")
+    if args.search or args.polish:
         save_store(circuits, args.store)
     missing = [b + 1 for b in range(8) if b not in circuits]
     if missing:
@@ -244,7 +277,8 @@ def main():
         circuits[b].polarities(boxes[b])
     with open(args.out, "w") as f:
         f.write(emit(circuits, boxes))
-    print(f"wrote {args.out}: total cost {sum(c.cost() for c in circuits.values())}")
+    print(f"wrote {args.out}: {sum(len(c.gates) for c in circuits.values())} gates, "
+          f"total cost {sum(c.cost() for c in circuits.values())}")
 
 
 if __name__ == "__main__":
