@@ -153,9 +153,13 @@ def build_tool(src: str) -> str:
 def run_search(exe, tab, seed, trials, budget, width=1) -> Circuit | None:
     res = subprocess.run([exe, str(seed), str(trials), str(budget)] + [str(v) for v in tab] + [str(width)],
                          stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, text=True)
-    if res.returncode != 0:
-        return None
-    return Circuit.parse(res.stdout.split("\n", 1)[1])
+    return last_circuit(res.stdout) if res.returncode == 0 else None
+
+
+def last_circuit(text: str) -> Circuit | None:
+    """The last circuit block ("cost ..." header, gate lines, "out" line) of a search's output."""
+    blocks = [b for b in re.split(r"^cost .*$", text, flags=re.M) if b.strip()]
+    return Circuit.parse(blocks[-1]) if blocks else None
 
 
 def run_polish(exe, args, tab, circuit: Circuit) -> Circuit | None:

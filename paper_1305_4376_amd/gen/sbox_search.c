@@ -6,6 +6,7 @@
  * Build-time tool.  Input: the S-box's 64 entries (argument list).  Output
  * (stdout): the best circuit found, one gate per line.  The Python driver
  * (gen_sbox.py) checks every circuit on all 64 inputs before emitting code.
+ * Each improvement is printed as it is found; the last block is the best.
  *
  * Functions are truth tables over the 64 input points (bit p = value at input
  * p; input variable x_i is bit 5-i of p, x_0 being the box's first input).
@@ -379,6 +380,15 @@ static void prune(circuit_t *C, int outs[4]) {
     *C = D;
 }
 
+/* One circuit block on stdout; the last block printed is the best one. */
+static void print_circuit(const circuit_t *C, const int outs[4], int cost) {
+    printf("cost %d gates %d\n", cost, C->n - 6);
+    for (int k = 6; k < C->n; k++)
+        printf("g %d %d %d %d %d\n", k, C->g[k].in[0], C->g[k].in[1], C->g[k].in[2], C->g[k].lut);
+    printf("out %d %d %d %d\n", outs[0], outs[1], outs[2], outs[3]);
+    fflush(stdout);
+}
+
 int main(int argc, char **argv) {
     if (argc < 66) {
         fprintf(stderr, "usage: sbox_search SEED TRIALS BUDGET2 s0 .. s63 [WIDTH]\n");
@@ -438,12 +448,8 @@ int main(int argc, char **argv) {
         if (gates < best.n - 6 || (gates == best.n - 6 && cost < best_cost) || best_cost >= (1 << 30)) {
             best_cost = cost; best = C; memcpy(best_outs, outs, sizeof outs);
             fprintf(stderr, "trial %d: gates %d cost %d\n", trial, gates, cost);
+            print_circuit(&best, best_outs, best_cost);  /* every improvement: a long run can be stopped */
         }
     }
-    if (best_cost >= (1 << 30)) return 1;
-    printf("cost %d gates %d\n", best_cost, best.n - 6);
-    for (int k = 6; k < best.n; k++)
-        printf("g %d %d %d %d %d\n", k, best.g[k].in[0], best.g[k].in[1], best.g[k].in[2], best.g[k].lut);
-    printf("out %d %d %d %d\n", best_outs[0], best_outs[1], best_outs[2], best_outs[3]);
-    return 0;
+    return best_cost >= (1 << 30) ? 1 : 0;
 }
