@@ -118,6 +118,18 @@ int tdes_ecb_decrypt(const void *dev_sched, const void *in, void *out, uint64_t 
 int tdes_ecb_run(const void *dev_sched, const void *in, void *out, uint64_t n_blocks, int direction,
                  int variant, void *stream);
 
+/*
+ * The paper's host loop (Listing 1.1, Section II.B): the same operation as
+ * tdes_ecb_run with the bitsliced kernel, issued as consecutive launches of
+ * chunk_blocks blocks each (the last one shorter), all on `stream`.  It exists
+ * to measure the launch-granularity effect of Table II on this GPU: every
+ * launch pays the launch overhead, which dominates for small chunks; a single
+ * launch per message (tdes_ecb_run) or per batch (tdes_ecb_batch) avoids it.
+ * Errors: as tdes_ecb_run; TDES_ERR_SIZE if chunk_blocks is 0.
+ */
+int tdes_ecb_chunked(const void *dev_sched, const void *in, void *out, uint64_t n_blocks, uint64_t chunk_blocks,
+                     int direction, void *stream);
+
 /* ---- block-parallel modes on the same round core ---- */
 
 /*

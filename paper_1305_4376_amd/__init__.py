@@ -24,7 +24,7 @@ __all__ = [
     "REQUEST_DTYPE", "COMPLETION_DTYPE", "tdes_server_create", "tdes_server_destroy", "tdes_server_now",
     "tdes_server_submit", "tdes_server_cancel", "tdes_server_poll", "tdes_server_wait_idle",
     "tdes_server_release", "tdes_server_stats", "tdes_server_run_trace", "tdes_ecb_host",
-    "tdes_ctr_crypt", "tdes_cbc_decrypt",
+    "tdes_ctr_crypt", "tdes_cbc_decrypt", "tdes_ecb_chunked",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtdes.so")
@@ -96,6 +96,7 @@ def load_library():
         "tdes_ecb_decrypt": ([vp, vp, vp, u64, vp], i32),
         "tdes_ecb_run": ([vp, vp, vp, u64, i32, i32, vp], i32),
         "tdes_ctr_crypt": ([vp, vp, vp, vp, u64, vp], i32),
+        "tdes_ecb_chunked": ([vp, vp, vp, u64, u64, i32, vp], i32),
         "tdes_cbc_decrypt": ([vp, vp, vp, vp, u64, vp], i32),
         "tdes_status_str": ([i32], ctypes.c_char_p),
         "tdes_fill_splitmix64": ([vp, u64, u64, u64, vp], i32),
@@ -202,6 +203,14 @@ def _iv_buffer(iv):
     if b is not None and len(b) != 8:
         raise ValueError("an IV is 8 bytes")
     return ctypes.create_string_buffer(b, 8) if b is not None else None
+
+
+def tdes_ecb_chunked(dev_sched, src, dst, chunk_blocks: int, n_blocks=None, direction: int = TDES_ENCRYPT,
+                     stream=None) -> None:
+    """The paper's host loop: one bitsliced launch per chunk of chunk_blocks blocks."""
+    n = _nblocks(src, n_blocks)
+    _check(load_library().tdes_ecb_chunked(_ptr(dev_sched), _ptr(src), _ptr(dst), n, int(chunk_blocks),
+                                           int(direction), _stream(stream, src)), "tdes_ecb_chunked")
 
 
 def tdes_ctr_crypt(dev_sched, iv, src, dst, n_blocks=None, stream=None) -> None:

@@ -91,6 +91,23 @@ extern "C" int tdes_ecb_decrypt(const void *dev_sched, const void *in, void *out
     return tdes_ecb_run(dev_sched, in, out, n_blocks, TDES_DECRYPT, TDES_VARIANT_AUTO, stream);
 }
 
+extern "C" int tdes_ecb_chunked(const void *dev_sched, const void *in, void *out, uint64_t n_blocks,
+                                uint64_t chunk_blocks, int direction, void *stream) {
+    const int rc = check_buffers(dev_sched, in, out, n_blocks);
+    if (rc != TDES_OK) return rc;
+    if (direction != TDES_ENCRYPT && direction != TDES_DECRYPT) return TDES_ERR_ARG;
+    if (chunk_blocks == 0) return TDES_ERR_SIZE;
+    const uint32_t *ks = static_cast<const uint32_t *>(dev_sched) + direction * tdes::kDirWords;
+    const uint8_t *src = static_cast<const uint8_t *>(in);
+    uint8_t *dst = static_cast<uint8_t *>(out);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (uint64_t first = 0; first < n_blocks; first += chunk_blocks) {
+        const uint64_t n = n_blocks - first < chunk_blocks ? n_blocks - first : chunk_blocks;
+        if (tdes::launch_bitslice(ks, src + 8 * first, dst + 8 * first, n, s) != hipSuccess) return TDES_ERR_HIP;
+    }
+    return TDES_OK;
+}
+
 namespace {
 
 uint64_t iv_value(const uint8_t iv[8]) {

@@ -208,3 +208,24 @@ def test_host_resident_message(pinned):
     # in place, decrypting back
     td.tdes_ecb_host(sched, dst, dst, n, td.TDES_DECRYPT, chunk_blocks=40000)
     assert np.array_equal(dst.numpy() if pinned else dst, host)
+
+
+def test_chunked_launches_equal_one_launch():
+    """The paper's host loop (one launch per chunk, a short last chunk) gives the single launch's output."""
+    n = 3 * 2048 * 5 + 777
+    seed = inputs.DATA_SEED_BASE + 90
+    keys = inputs.key_triple(inputs.KEY_SEED_BASE + 90)
+    sched = _gpu.device_sched(*keys)
+    src = _gpu.device_message(seed, n)
+    one = torch.empty_like(src)
+    td.tdes_ecb_encrypt(sched, src, one)
+    for chunk in (1, 100, 2048, 4096 + 8, n, 2 * n):
+        print(f"[parity] chunked chunk={chunk}", flush=True)
+        out = torch.empty_like(src)
+        td.tdes_ecb_chunked(sched, src, out, chunk, n) if chunk >= 100 else td.tdes_ecb_chunked(sched, src[:8 * 5000], out[:8 * 5000], chunk, 5000)
+        torch.cuda.synchronize()
+        m = n if chunk >= 100 else 5000
+        assert torch.equal(out[:8 * m], one[:8 * m]), chunk
+    with pytest.raises(td.TdesError) as e:
+        td.tdes_ecb_chunked(sched, src, one, 0, n)
+    assert e.value.code == -4
