@@ -253,6 +253,33 @@ def bench_host_path(td, torch, sched, dev, reps=3):
             "ms": round(dt * 1e3, 3)}
 
 
+def bench_sizes(td, torch, sched, dev):
+    """Kernel time of one launch against message size, both variants (HIP events, mean of repeats):
+    where the bitsliced kernel's fixed per-tile latency stops mattering."""
+    out = []
+    buf = torch.empty((1 << 24) * 8, dtype=torch.uint8, device=dev)
+    td.tdes_fill_splitmix64(buf, 1 << 24, DATA_SEED, 0)
+    dst = torch.empty_like(buf)
+    for log_n in range(8, 25, 2):
+        n = 1 << log_n
+        row = {"blocks": n}
+        for name, v in (("table", td.TDES_VARIANT_TABLE), ("bitslice", td.TDES_VARIANT_BITSLICE)):
+            reps = 20
+            for _ in range(3):
+                td.tdes_ecb_run(sched, buf, dst, n, td.TDES_ENCRYPT, v)
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+            for a, b in ev:
+                a.record()
+                td.tdes_ecb_run(sched, buf, dst, n, td.TDES_ENCRYPT, v)
+                b.record()
+            torch.cuda.synchronize()
+            us = sum(a.elapsed_time(b) for a, b in ev) / reps * 1e3
+            row[name + "_us"] = round(us, 2)
+            row[name + "_gbs"] = round(n * 8 / us / 1e3, 3)
+        out.append(row)
+    return out
+
+
 def bench_paper_scheme(td, torch, sched, dev):
     """The paper's host loop (Listing 1.1): one launch per chunk of a 512 MiB message, swept over the
     chunk size as in Table II, issued by the library (tdes_ecb_chunked).  Sizes that need more than
@@ -336,7 +363,7 @@ def main():
         torch.cuda.synchronize()
         ms = sum(a.elapsed_time(b) for a, b in ev) / len(ev)
         modes[name] = {"gbs": round(N_BLOCKS * 8 / (ms / 1e3) / 1e9, 3), "kernel_ms": round(ms, 4)}
-    # The timed run: the shipped default (TDES_VARIANT_AUTO = bitsliced).
+    # The timed run: the shipped default (TDES_VARIANT_AUTO: the bitsliced kernel at this size).
     wall, launch_ms = time_plain(td, torch, sched, src, ct, pt, td.TDES_VARIANT_AUTO, args.steps, args.warmup)
     roundtrip_ok = bool(torch.equal(pt, src))
     value = bytes_per_step * args.steps / wall / 1e9
@@ -368,6 +395,7 @@ def main():
     if not args.no_host_path:
         line["host_path"] = bench_host_path(td, torch, sched, dev)
     if not args.no_paper_ablation:
+        line["sizes"] = bench_sizes(td, torch, sched, dev)
         line["paper_scheme"] = bench_paper_scheme(td, torch, sched, dev)
         torch.cuda.empty_cache()
     capacity = value * 1e9

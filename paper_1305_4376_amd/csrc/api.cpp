@@ -8,6 +8,11 @@
 
 namespace tdes {
 
+hipError_t launch_auto(const uint32_t *ks, const uint8_t *in, uint8_t *out, uint64_t n_blocks, hipStream_t stream) {
+    return n_blocks < kAutoTableBelow ? launch_table(ks, in, out, n_blocks, stream)
+                                      : launch_bitslice(ks, in, out, n_blocks, stream);
+}
+
 namespace {
 constexpr int kMaxDevices = 64;
 std::once_flag g_dev_once[kMaxDevices];
@@ -50,10 +55,13 @@ int check_buffers(const void *dev_sched, const void *in, const void *out, uint64
     return TDES_OK;
 }
 
-// The bitsliced kernel is the default: on MI355X it runs the 1 GiB message about
-// 3x faster than the table kernel (765-789 vs 254-261 GB/s, encrypt + decrypt).
-int resolve_variant(int variant) {
-    if (variant == TDES_VARIANT_AUTO) return TDES_VARIANT_BITSLICE;
+// The automatic choice, on MI355X measurements of one launch (encrypt, kernel
+// time): the bitsliced kernel costs about 40 us for anything up to 2^19 blocks
+// (one wave runs a whole 2048-block tile through all 48 rounds) and then
+// scales at about 800 GB/s; the table kernel costs 16-19 us up to 2^18 blocks
+// and scales at about 260 GB/s.  They meet near 2^20 blocks (43 vs 45 us).
+int resolve_variant(int variant, uint64_t n_blocks) {
+    if (variant == TDES_VARIANT_AUTO) return n_blocks < tdes::kAutoTableBelow ? TDES_VARIANT_TABLE : TDES_VARIANT_BITSLICE;
     return variant;
 }
 
@@ -72,7 +80,7 @@ extern "C" int tdes_ecb_run(const void *dev_sched, const void *in, void *out, ui
     uint8_t *dst = static_cast<uint8_t *>(out);
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t err;
-    switch (resolve_variant(variant)) {
+    switch (resolve_variant(variant, n_blocks)) {
         case TDES_VARIANT_BITSLICE:
             err = tdes::launch_bitslice(ks, src, dst, n_blocks, s);
             break;

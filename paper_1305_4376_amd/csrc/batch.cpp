@@ -333,7 +333,7 @@ extern "C" int tdes_ecb_batch(tdes_ctx *c, const tdes_job *jobs, uint32_t n_jobs
             const tdes_job &x = jobs[j];
             if (x.n_blocks == 0) continue;
             const uint32_t *ks = table + x.sched_idx * (TDES_SCHED_BYTES / 4) + x.direction * tdes::kDirWords;
-            if (tdes::launch_bitslice(ks, base + x.in_off, base + x.out_off, x.n_blocks, s) != hipSuccess)
+            if (tdes::launch_auto(ks, base + x.in_off, base + x.out_off, x.n_blocks, s) != hipSuccess)
                 return TDES_ERR_HIP;
         }
         return TDES_OK;

@@ -29,6 +29,9 @@ hipError_t launch_table(const uint32_t *ks, const uint8_t *in, uint8_t *out, uin
                         hipStream_t stream);
 hipError_t launch_bitslice(const uint32_t *ks, const uint8_t *in, uint8_t *out, uint64_t n_blocks,
                            hipStream_t stream);
+// TDES_VARIANT_AUTO: the table kernel below this many blocks, the bitsliced one from it on.
+constexpr uint64_t kAutoTableBelow = 1ull << 20;
+hipError_t launch_auto(const uint32_t *ks, const uint8_t *in, uint8_t *out, uint64_t n_blocks, hipStream_t stream);
 // Block-parallel modes (bitsliced): ks is the encryption half for CTR and the
 // decryption half for CBC decryption; iv is the 8 IV bytes read as a big-endian integer.
 hipError_t launch_ctr(const uint32_t *ks, const uint8_t *in, uint8_t *out, uint64_t n_blocks, uint64_t iv,
