@@ -1,7 +1,7 @@
 """Generate the bitsliced kernel's S-box circuits (csrc/sbox_circuits.inc).
 
     python -m paper_1305_4376_amd.gen.gen_sbox [--search TRIALS] [--budget N] [--seeds K] [--width W]
-                                               [--polish ITERATIONS]
+                                               [--polish ITERATIONS] [--lns ITERATIONS]
 
 Each of the eight DES S-boxes (read from csrc/des_spec.h, the table the other
 kernel uses too) becomes a function of six bit planes that XORs its four
@@ -12,7 +12,8 @@ whose bit (4a + 2b + c) is the output for operand bits a, b, c.
 The circuits come from sbox_search.c (a randomized decomposition search
 written for this purpose; see that file).  The chosen ones are stored in
 sbox_circuits.txt; with --search the search runs again and a circuit replaces
-the stored one only if it has fewer gates (then a lower cost).  --polish runs
+the stored one only if it has fewer gates (then a lower cost).  --lns runs
+the search's large-neighbourhood mode from each stored circuit.  --polish runs
 two local improvers on the stored circuits: sbox_cgp.c (evolution with
 resubstitution) and sbox_resyn.c (resynthesis of fanout-free cones).  Every
 circuit is checked on all 64 inputs before any code is written.
@@ -162,13 +163,13 @@ def last_circuit(text: str) -> Circuit | None:
     return Circuit.parse(blocks[-1]) if blocks else None
 
 
-def run_polish(exe, args, tab, circuit: Circuit) -> Circuit | None:
-    """Feed a stored circuit to a local improver; return its output circuit (or None)."""
+def run_polish(exe, args, tab, circuit: Circuit, last: bool = False) -> Circuit | None:
+    """Feed a stored circuit to an improver; return its (last printed) output circuit, or None."""
     res = subprocess.run([exe] + [str(a) for a in args] + [str(v) for v in tab], input=circuit.dump(),
                          stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, text=True)
     if res.returncode != 0 or "\n" not in res.stdout:
         return None
-    return Circuit.parse(res.stdout.split("\n", 1)[1])
+    return last_circuit(res.stdout) if last else Circuit.parse(res.stdout.split("\n", 1)[1])
 
 
 def emit(circuits: dict[int, Circuit], boxes) -> str:
@@ -234,6 +235,7 @@ def main():
     ap.add_argument("--seeds", type=int, default=8)
     ap.add_argument("--width", type=int, default=1, help="search: attempts per output, best kept")
     ap.add_argument("--polish", type=int, default=0, help="iterations of the local improvers (0: none)")
+    ap.add_argument("--lns", type=int, default=0, help="iterations of the search's large-neighbourhood mode (0: none)")
     ap.add_argument("--boxes", default="1,2,3,4,5,6,7,8")
     ap.add_argument("--store", default=STORE, help="circuit store to read and update")
     ap.add_argument("--out", default=OUT_INC, help="generated HIP include")
@@ -261,6 +263,15 @@ def main():
                                                                    args.search, args.budget, args.width)), jobs))
         for b, c in results:
             accept(b, c, "search")
+    if args.lns:
+        exe = build_tool(SEARCH_SRC)
+        jobs = [(b, s) for b in todo if b in circuits for s in range(args.seeds)]
+        with ThreadPoolExecutor(max_workers=workers) as pool:
+            results = list(pool.map(lambda bs: (bs[0], run_polish(
+                exe, [7000 * bs[0] + bs[1] + 1, args.lns, args.budget], boxes[bs[0]] + [max(args.width, 1), 1],
+                circuits[bs[0]], last=True)), jobs))
+        for b, c in results:
+            accept(b, c, "large-neighbourhood search")
     if args.polish:
         cgp, resyn = build_tool(CGP_SRC), build_tool(RESYN_SRC)
         jobs = [(b, s) for b in todo if b in circuits for s in range(args.seeds)]

@@ -7,6 +7,8 @@
  * (stdout): the best circuit found, one gate per line.  The Python driver
  * (gen_sbox.py) checks every circuit on all 64 inputs before emitting code.
  * Each improvement is printed as it is found; the last block is the best.
+ * With IMPROVE set it instead improves a given circuit (large-neighbourhood
+ * search: re-realize one output at a time from the others' gates).
  *
  * Functions are truth tables over the 64 input points (bit p = value at input
  * p; input variable x_i is bit 5-i of p, x_0 being the box's first input).
@@ -380,6 +382,87 @@ static void prune(circuit_t *C, int outs[4]) {
     *C = D;
 }
 
+static int circuit_cost(const circuit_t *C, const int outs[4]) {
+    int extra = 0;
+    for (int j = 0; j < 4; j++) {
+        int o = outs[j];
+        if (o < 6 || distinct_operands(&C->g[o]) == 3 || uses(C, o) > 0) extra++;
+        for (int i = 0; i < j; i++) if (outs[i] == o) extra++;
+    }
+    return C->n - 6 + extra;
+}
+
+static void print_circuit(const circuit_t *C, const int outs[4], int cost);
+
+/*
+ * Large-neighbourhood search from a circuit read on stdin (the format printed
+ * below): repeatedly pick an output, drop the gates only it uses, realize it
+ * again from the rest (best of `width` attempts), and keep the result if it
+ * has no more gates (equal ones too, so the circuit drifts).
+ */
+static int improve(const tt target[4], int iters, int budget2, int width) {
+    circuit_t C;
+    memset(&C, 0, sizeof C);
+    C.n = 6;
+    for (int i = 0; i < 6; i++) { C.val[i] = input_tt(i); C.g[i].in[0] = C.g[i].in[1] = C.g[i].in[2] = -1; }
+    int outs[4] = {-1, -1, -1, -1};
+    char line[256];
+    while (fgets(line, sizeof line, stdin)) {
+        int node, a, b, c, lut, o0, o1, o2, o3;
+        if (sscanf(line, "g %d %d %d %d %d", &node, &a, &b, &c, &lut) == 5) {
+            if (node != C.n || a >= node || b >= node || c >= node) { fprintf(stderr, "bad gate line\n"); return 1; }
+            add_gate(&C, a, b, c, lut);
+        } else if (sscanf(line, "out %d %d %d %d", &o0, &o1, &o2, &o3) == 4) {
+            outs[0] = o0; outs[1] = o1; outs[2] = o2; outs[3] = o3;
+        }
+    }
+    for (int j = 0; j < 4; j++)
+        if (outs[j] < 0 || outs[j] >= C.n || (C.val[outs[j]] != target[j] && ~C.val[outs[j]] != target[j])) {
+            fprintf(stderr, "start circuit is not correct\n");
+            return 1;
+        }
+    int cur_cost = circuit_cost(&C, outs);
+    int best_gates = C.n - 6, best_cost = cur_cost;
+    fprintf(stderr, "start: gates %d cost %d\n", best_gates, best_cost);
+    print_circuit(&C, outs, best_cost);
+    for (int it = 0; it < iters; it++) {
+        const int j = rndint(4);
+        circuit_t D = C;
+        int o[4];
+        memcpy(o, outs, sizeof o);
+        /* keep the other outputs' cones only */
+        int others[4], m = 0;
+        for (int q = 0; q < 4; q++) if (q != j) others[m++] = o[q];
+        others[3] = others[0];
+        prune(&D, others);
+        for (int q = 0, k = 0; q < 4; q++) if (q != j) o[q] = others[k++];
+        circuit_t keep;
+        int keep_k = -1;
+        for (int w = 0; w < width; w++) {
+            circuit_t A = D;
+            int k = realize_top(&A, target[j], ~0ull, budget2);
+            if (k < 0) continue;
+            if (keep_k < 0 || A.n < keep.n) { keep = A; keep_k = k; }
+        }
+        if (keep_k < 0) continue;
+        o[j] = keep_k;
+        prune(&keep, o);
+        const int g = keep.n - 6, cost = circuit_cost(&keep, o);
+        if (g < C.n - 6 || (g == C.n - 6 && cost <= cur_cost)) {
+            C = keep;
+            memcpy(outs, o, sizeof o);
+            cur_cost = cost;
+            if (g < best_gates || (g == best_gates && cost < best_cost)) {
+                best_gates = g;
+                best_cost = cost;
+                fprintf(stderr, "iter %d: gates %d cost %d\n", it, g, cost);
+                print_circuit(&C, outs, cost);
+            }
+        }
+    }
+    return 0;
+}
+
 /* One circuit block on stdout; the last block printed is the best one. */
 static void print_circuit(const circuit_t *C, const int outs[4], int cost) {
     printf("cost %d gates %d\n", cost, C->n - 6);
@@ -391,7 +474,8 @@ static void print_circuit(const circuit_t *C, const int outs[4], int cost) {
 
 int main(int argc, char **argv) {
     if (argc < 66) {
-        fprintf(stderr, "usage: sbox_search SEED TRIALS BUDGET2 s0 .. s63 [WIDTH]\n");
+        fprintf(stderr, "usage: sbox_search SEED TRIALS BUDGET2 s0 .. s63 [WIDTH [IMPROVE]]\n"
+                        "  IMPROVE > 0: large-neighbourhood search from a circuit on stdin, TRIALS iterations\n");
         return 2;
     }
     const int width = argc > 67 ? atoi(argv[67]) : 1;  /* attempts per output, best kept */
@@ -409,6 +493,7 @@ int main(int argc, char **argv) {
     circuit_t best;
     best.n = 6;
     int best_cost = 1 << 30, best_outs[4] = {0};
+    if (argc > 68 && atoi(argv[68]) > 0) return improve(target, trials, budget2, width);
     for (int trial = 0; trial < trials; trial++) {
         g_allow_bidec = (int)(rnd() % 3 == 0);
         circuit_t C;
