@@ -41,6 +41,18 @@ def _run(cmd, verbose):
         raise subprocess.CalledProcessError(res.returncode, cmd)
 
 
+UNITS_SRC = os.path.join(ROOT, "tests", "units", "k_units.hip")
+UNITS_LIB = os.path.join(ROOT, "tests", "units", "libtdes_units.so")
+
+
+def build_units(verbose: bool = False) -> str:
+    """The GPU unit tests' kernels (test infrastructure): tests/units/libtdes_units.so."""
+    tmp = UNITS_LIB + ".tmp"
+    _run([HIPCC, *COMMON, "-x", "hip", "-shared", "-o", tmp, UNITS_SRC], verbose)
+    os.replace(tmp, UNITS_LIB)
+    return UNITS_LIB
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     objs = []
@@ -58,3 +70,4 @@ def build(verbose: bool = False) -> str:
 
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))
+    print(build_units(verbose="-v" in sys.argv))

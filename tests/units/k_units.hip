@@ -1,0 +1,134 @@
+// k_units.hip -- unit kernels for the GPU tests: the bitsliced core's pieces on the device.
+//
+// Test infrastructure, built beside the library (build.py) into
+// tests/units/libtdes_units.so and called only from tests/test_gpu_units.py.
+// Each entry point launches one single-lane kernel over caller-owned device
+// buffers and returns 0, or -1 if the launch failed.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../paper_1305_4376_amd/csrc/bitslice_core.h"
+
+namespace {
+
+using namespace tdes_bs;
+
+template <int S>
+__device__ void run_box(const uint32_t (&x)[6], uint32_t *o, int variant) {
+    uint32_t o0 = 0, o1 = 0, o2 = 0, o3 = 0;
+    const uint32_t m = variant == 2 ? ~0u : 0u;
+    if (variant == 0) {
+        if constexpr (S == 0) sbox0(x[0], x[1], x[2], x[3], x[4], x[5], o0, o1, o2, o3);
+        if constexpr (S == 1) sbox1(x[0], x[1], x[2], x[3], x[4], x[5], o0, o1, o2, o3);
+        if constexpr (S == 2) sbox2(x[0], x[1], x[2], x[3], x[4], x[5], o0, o1, o2, o3);
+        if constexpr (S == 3) sbox3(x[0], x[1], x[2], x[3], x[4], x[5], o0, o1, o2, o3);
+        if constexpr (S == 4) sbox4(x[0], x[1], x[2], x[3], x[4], x[5], o0, o1, o2, o3);
+        if constexpr (S == 5) sbox5(x[0], x[1], x[2], x[3], x[4], x[5], o0, o1, o2, o3);
+        if constexpr (S == 6) sbox6(x[0], x[1], x[2], x[3], x[4], x[5], o0, o1, o2, o3);
+        if constexpr (S == 7) sbox7(x[0], x[1], x[2], x[3], x[4], x[5], o0, o1, o2, o3);
+    } else {
+        if constexpr (S == 0) sbox0_m(x[0], x[1], x[2], x[3], x[4], x[5], o0, o1, o2, o3, m, m, m, m);
+        if constexpr (S == 1) sbox1_m(x[0], x[1], x[2], x[3], x[4], x[5], o0, o1, o2, o3, m, m, m, m);
+        if constexpr (S == 2) sbox2_m(x[0], x[1], x[2], x[3], x[4], x[5], o0, o1, o2, o3, m, m, m, m);
+        if constexpr (S == 3) sbox3_m(x[0], x[1], x[2], x[3], x[4], x[5], o0, o1, o2, o3, m, m, m, m);
+        if constexpr (S == 4) sbox4_m(x[0], x[1], x[2], x[3], x[4], x[5], o0, o1, o2, o3, m, m, m, m);
+        if constexpr (S == 5) sbox5_m(x[0], x[1], x[2], x[3], x[4], x[5], o0, o1, o2, o3, m, m, m, m);
+        if constexpr (S == 6) sbox6_m(x[0], x[1], x[2], x[3], x[4], x[5], o0, o1, o2, o3, m, m, m, m);
+        if constexpr (S == 7) sbox7_m(x[0], x[1], x[2], x[3], x[4], x[5], o0, o1, o2, o3, m, m, m, m);
+    }
+    o[0] = o0; o[1] = o1; o[2] = o2; o[3] = o3;
+}
+
+// out[((box * 3 + variant) * 2 + half) * 4 + j]: output plane j of the box for the 32 inputs
+// 32 * half + t (bit t), starting from zero planes; variant 0: plain circuit, 1: masked with
+// m = 0, 2: masked with m = ~0.
+__global__ void sbox_kernel(uint32_t *out) {
+    for (int half = 0; half < 2; half++) {
+        uint32_t x[6];
+        for (int i = 0; i < 6; i++) {
+            x[i] = 0;
+            for (int t = 0; t < 32; t++)
+                if (((32 * half + t) >> (5 - i)) & 1) x[i] |= 1u << t;
+        }
+        for (int v = 0; v < 3; v++) {
+            run_box<0>(x, out + ((0 * 3 + v) * 2 + half) * 4, v);
+            run_box<1>(x, out + ((1 * 3 + v) * 2 + half) * 4, v);
+            run_box<2>(x, out + ((2 * 3 + v) * 2 + half) * 4, v);
+            run_box<3>(x, out + ((3 * 3 + v) * 2 + half) * 4, v);
+            run_box<4>(x, out + ((4 * 3 + v) * 2 + half) * 4, v);
+            run_box<5>(x, out + ((5 * 3 + v) * 2 + half) * 4, v);
+            run_box<6>(x, out + ((6 * 3 + v) * 2 + half) * 4, v);
+            run_box<7>(x, out + ((7 * 3 + v) * 2 + half) * 4, v);
+        }
+    }
+}
+
+__global__ void transpose_kernel(const uint32_t *in, uint32_t *out) {
+    uint32_t w[32];
+    for (int i = 0; i < 32; i++) w[i] = in[i];
+    transpose32(w);
+    for (int i = 0; i < 32; i++) out[i] = w[i];
+}
+
+// 32 blocks (a[j] = bytes 0..3, b[j] = bytes 4..7 of block j) through `rounds` rounds of one DES
+// stage with per-lane round words ks (32 words); out[i * 64 + k]: after round i (i = 0: before the
+// first), plane k of the half that started as L (k < 32) or as R (k >= 32).
+__global__ void rounds_kernel(const uint32_t *blocks, const uint32_t *ks, int rounds, uint32_t *out) {
+    uint32_t a[32], b[32], l[32], r[32];
+    for (int j = 0; j < 32; j++) { a[j] = blocks[2 * j]; b[j] = blocks[2 * j + 1]; }
+    transpose32(a);
+    transpose32(b);
+    for (int k = 0; k < 32; k++) {
+        const int pl = kMaps.l0[k], pr = kMaps.r0[k];
+        l[k] = pl < 32 ? a[pl] : b[pl - 32];
+        r[k] = pr < 32 ? a[pr] : b[pr - 32];
+    }
+    for (int k = 0; k < 32; k++) { out[k] = l[k]; out[32 + k] = r[k]; }
+    for (int i = 0; i < rounds; i++) {
+        if (i % 2 == 0) feistel<true>(l, r, ks[2 * i], ks[2 * i + 1]);
+        else feistel<true>(r, l, ks[2 * i], ks[2 * i + 1]);
+        for (int k = 0; k < 32; k++) { out[(i + 1) * 64 + k] = l[k]; out[(i + 1) * 64 + 32 + k] = r[k]; }
+    }
+}
+
+// One DES stage with folded masks (the wave-key path): out = the 64 planes (L16 then R16).
+__global__ void folded_stage_kernel(const uint32_t *blocks, const uint32_t *dir_words, int stage, uint32_t *out) {
+    uint32_t a[32], b[32], l[32], r[32];
+    for (int j = 0; j < 32; j++) { a[j] = blocks[2 * j]; b[j] = blocks[2 * j + 1]; }
+    transpose32(a);
+    transpose32(b);
+    for (int k = 0; k < 32; k++) {
+        const int pl = kMaps.l0[k], pr = kMaps.r0[k];
+        l[k] = pl < 32 ? a[pl] : b[pl - 32];
+        r[k] = pr < 32 ? a[pr] : b[pr - 32];
+    }
+    des_stage_folded(l, r, dir_words + kFoldBase, stage);
+    for (int k = 0; k < 32; k++) { out[k] = l[k]; out[32 + k] = r[k]; }
+}
+
+int status() { return hipGetLastError() == hipSuccess && hipDeviceSynchronize() == hipSuccess ? 0 : -1; }
+
+}  // namespace
+
+extern "C" int units_sbox(uint32_t *dev_out) {
+    hipLaunchKernelGGL(sbox_kernel, dim3(1), dim3(1), 0, 0, dev_out);
+    return status();
+}
+
+extern "C" int units_transpose(const uint32_t *dev_in, uint32_t *dev_out) {
+    hipLaunchKernelGGL(transpose_kernel, dim3(1), dim3(1), 0, 0, dev_in, dev_out);
+    return status();
+}
+
+extern "C" int units_rounds(const uint32_t *dev_blocks, const uint32_t *dev_ks, int rounds, uint32_t *dev_out) {
+    if (rounds < 0 || rounds > 16) return -1;
+    hipLaunchKernelGGL(rounds_kernel, dim3(1), dim3(1), 0, 0, dev_blocks, dev_ks, rounds, dev_out);
+    return status();
+}
+
+extern "C" int units_folded_stage(const uint32_t *dev_blocks, const uint32_t *dev_dir_words, int stage,
+                                  uint32_t *dev_out) {
+    if (stage < 0 || stage > 2) return -1;
+    hipLaunchKernelGGL(folded_stage_kernel, dim3(1), dim3(1), 0, 0, dev_blocks, dev_dir_words, stage, dev_out);
+    return status();
+}
