@@ -396,9 +396,10 @@ static void print_circuit(const circuit_t *C, const int outs[4], int cost);
 
 /*
  * Large-neighbourhood search from a circuit read on stdin (the format printed
- * below): repeatedly pick an output, drop the gates only it uses, realize it
- * again from the rest (best of `width` attempts), and keep the result if it
- * has no more gates (equal ones too, so the circuit drifts).
+ * below): repeatedly pick an output (a third of the time two), drop the gates
+ * only they use, realize them again from the rest (best of `width` attempts
+ * each), and keep the result if it has no more gates (equal ones too, so the
+ * circuit drifts).
  */
 static int improve(const tt target[4], int iters, int budget2, int width) {
     circuit_t C;
@@ -426,26 +427,36 @@ static int improve(const tt target[4], int iters, int budget2, int width) {
     fprintf(stderr, "start: gates %d cost %d\n", best_gates, best_cost);
     print_circuit(&C, outs, best_cost);
     for (int it = 0; it < iters; it++) {
-        const int j = rndint(4);
+        /* drop one output, or two, and realize them again from the rest */
+        int drop[4] = {0, 0, 0, 0}, order[2], nd = 1 + (rndint(3) == 0);
+        order[0] = rndint(4);
+        do { order[1] = rndint(4); } while (order[1] == order[0]);
+        for (int d = 0; d < nd; d++) drop[order[d]] = 1;
         circuit_t D = C;
         int o[4];
         memcpy(o, outs, sizeof o);
-        /* keep the other outputs' cones only */
-        int others[4], m = 0;
-        for (int q = 0; q < 4; q++) if (q != j) others[m++] = o[q];
-        others[3] = others[0];
-        prune(&D, others);
-        for (int q = 0, k = 0; q < 4; q++) if (q != j) o[q] = others[k++];
-        circuit_t keep;
-        int keep_k = -1;
-        for (int w = 0; w < width; w++) {
-            circuit_t A = D;
-            int k = realize_top(&A, target[j], ~0ull, budget2);
-            if (k < 0) continue;
-            if (keep_k < 0 || A.n < keep.n) { keep = A; keep_k = k; }
+        int kept[4], m = 0;
+        for (int q = 0; q < 4; q++) if (!drop[q]) kept[m++] = o[q];
+        for (int q = m; q < 4; q++) kept[q] = kept[0];
+        prune(&D, kept);
+        for (int q = 0, k = 0; q < 4; q++) if (!drop[q]) o[q] = kept[k++];
+        int ok = 1;
+        for (int d = 0; d < nd && ok; d++) {
+            const int j = order[d];
+            circuit_t keep;
+            int keep_k = -1;
+            for (int w = 0; w < width; w++) {
+                circuit_t A = D;
+                int k = realize_top(&A, target[j], ~0ull, budget2);
+                if (k < 0) continue;
+                if (keep_k < 0 || A.n < keep.n) { keep = A; keep_k = k; }
+            }
+            if (keep_k < 0) { ok = 0; break; }
+            D = keep;
+            o[j] = keep_k;
         }
-        if (keep_k < 0) continue;
-        o[j] = keep_k;
+        if (!ok) continue;
+        circuit_t keep = D;
         prune(&keep, o);
         const int g = keep.n - 6, cost = circuit_cost(&keep, o);
         if (g < C.n - 6 || (g == C.n - 6 && cost <= cur_cost)) {
