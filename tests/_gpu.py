@@ -11,7 +11,7 @@ import paper_1305_4376_amd as td
 from paper_1305_4376_amd import inputs
 
 DEV = torch.device("cuda", 0)
-# Host threads for the oracle: the GPU machine's share of cores, at most 16.
+# Host threads for the oracle: the cores this process may use, at most 16.
 ORACLE_THREADS = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else 8))
 
 
