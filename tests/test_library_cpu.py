@@ -214,3 +214,61 @@ def test_folded_key_words_match_oracle_subkeys(keying):
             for st in range(3):
                 assert int(fold[96 + st]) == sum(bit(order[16 * st], first[q]) << q for q in range(32))
                 assert int(fold[99 + st]) == sum(bit(order[16 * st + 15], first[q]) << q for q in range(32))
+
+
+INC = os.path.join(os.path.dirname(SPEC), "sbox_circuits.inc")
+
+
+def _eval_circuit_functions():
+    """Evaluate every function of the generated S-box include on all 64 inputs, as 64-bit truth
+    tables (bit p = input p, input variable i = bit 5 - i of p).  v_bitop3_b32's table bit is
+    4a + 2b + c for operand bits a, b, c."""
+    full = (1 << 64) - 1
+    ins = [sum(1 << p for p in range(64) if (p >> (5 - i)) & 1) for i in range(6)]
+
+    def bitop3(a, b, c, lut):
+        r = 0
+        for m in range(8):
+            if (lut >> m) & 1:
+                r |= (a if m & 4 else full ^ a) & (b if m & 2 else full ^ b) & (c if m & 1 else full ^ c)
+        return r
+
+    funcs = {}
+    for m in re.finditer(r"void (sbox\d(?:_m)?)\(([^)]*)\) \{(.*?)\n\}", open(INC).read(), flags=re.S):
+        funcs[m.group(1)] = m.group(3)
+    results = {}
+    for name, body in funcs.items():
+        for mask in ((0, full) if name.endswith("_m") else (0,)):
+            env = {f"n{i}": ins[i] for i in range(6)}
+            env.update({f"o{j}": 0 for j in range(4)}, **{f"m{j}": mask for j in range(4)})
+            for line in body.strip().splitlines():
+                line = line.strip().rstrip(";")
+                if g := re.fullmatch(r"(?:const uint32_t )?(\w+) = __builtin_amdgcn_bitop3_b32\((\w+), (\w+), (\w+), (0x[0-9A-F]+)\)", line):
+                    env[g.group(1)] = bitop3(env[g.group(2)], env[g.group(3)], env[g.group(4)], int(g.group(5), 16))
+                elif g := re.fullmatch(r"(\w+) \^= (\w+)", line):
+                    env[g.group(1)] ^= env[g.group(2)]
+                elif g := re.fullmatch(r"(\w+) = ~\((\w+) \^ (\w+)\)", line):
+                    env[g.group(1)] = full ^ (env[g.group(2)] ^ env[g.group(3)])
+                else:
+                    raise AssertionError(f"unexpected statement in {name}: {line}")
+            results[(name, mask)] = [env[f"o{j}"] for j in range(4)]
+    return results
+
+
+def test_generated_sbox_circuits_equal_oracle_tables():
+    """The S-box circuits as the kernels compile them (sbox_circuits.inc), on all 64 inputs, plain
+    and with key masks 0 and ~0, against the oracle's S-box table."""
+    table = oracle.table("SBOX")
+    full = (1 << 64) - 1
+    results = _eval_circuit_functions()
+    assert len(results) == 8 + 16
+    for b in range(8):
+        want = [0] * 4
+        for p in range(64):
+            s = table[b * 64 + (((p >> 5) & 1) * 2 + (p & 1)) * 16 + ((p >> 1) & 15)]
+            for j in range(4):
+                if (s >> (3 - j)) & 1:
+                    want[j] |= 1 << p
+        assert results[(f"sbox{b}", 0)] == want, b
+        assert results[(f"sbox{b}_m", 0)] == want, b
+        assert results[(f"sbox{b}_m", full)] == [w ^ full for w in want], b
