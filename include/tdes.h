@@ -125,15 +125,17 @@ int tdes_ecb_run(const void *dev_sched, const void *in, void *out, uint64_t n_bl
 
 /*
  * The paper's host loop (Listing 1.1, Section II.B): the same operation as
- * tdes_ecb_run with the bitsliced kernel, issued as consecutive launches of
- * chunk_blocks blocks each (the last one shorter), all on `stream`.  It exists
- * to measure the launch-granularity effect of Table II on this GPU: every
- * launch pays the launch overhead, which dominates for small chunks; a single
- * launch per message (tdes_ecb_run) or per batch (tdes_ecb_batch) avoids it.
+ * tdes_ecb_run, issued as consecutive launches of chunk_blocks blocks each
+ * (the last one shorter), all on `stream`, each with `variant`
+ * (TDES_VARIANT_AUTO chooses by the chunk's size).  It exists to measure the
+ * launch-granularity effect of Table II on this GPU: every launch pays the
+ * launch overhead and the kernel's latency, which dominate for small chunks;
+ * a single launch per message (tdes_ecb_run) or per batch (tdes_ecb_batch)
+ * avoids them.
  * Errors: as tdes_ecb_run; TDES_ERR_SIZE if chunk_blocks is 0.
  */
 int tdes_ecb_chunked(const void *dev_sched, const void *in, void *out, uint64_t n_blocks, uint64_t chunk_blocks,
-                     int direction, void *stream);
+                     int direction, int variant, void *stream);
 
 /* ---- block-parallel modes on the same round core ---- */
 

@@ -96,7 +96,7 @@ def load_library():
         "tdes_ecb_decrypt": ([vp, vp, vp, u64, vp], i32),
         "tdes_ecb_run": ([vp, vp, vp, u64, i32, i32, vp], i32),
         "tdes_ctr_crypt": ([vp, vp, vp, vp, u64, vp], i32),
-        "tdes_ecb_chunked": ([vp, vp, vp, u64, u64, i32, vp], i32),
+        "tdes_ecb_chunked": ([vp, vp, vp, u64, u64, i32, i32, vp], i32),
         "tdes_cbc_decrypt": ([vp, vp, vp, vp, u64, vp], i32),
         "tdes_status_str": ([i32], ctypes.c_char_p),
         "tdes_fill_splitmix64": ([vp, u64, u64, u64, vp], i32),
@@ -206,11 +206,11 @@ def _iv_buffer(iv):
 
 
 def tdes_ecb_chunked(dev_sched, src, dst, chunk_blocks: int, n_blocks=None, direction: int = TDES_ENCRYPT,
-                     stream=None) -> None:
-    """The paper's host loop: one bitsliced launch per chunk of chunk_blocks blocks."""
+                     variant: int = TDES_VARIANT_AUTO, stream=None) -> None:
+    """The paper's host loop: one launch per chunk of chunk_blocks blocks."""
     n = _nblocks(src, n_blocks)
     _check(load_library().tdes_ecb_chunked(_ptr(dev_sched), _ptr(src), _ptr(dst), n, int(chunk_blocks),
-                                           int(direction), _stream(stream, src)), "tdes_ecb_chunked")
+                                           int(direction), int(variant), _stream(stream, src)), "tdes_ecb_chunked")
 
 
 def tdes_ctr_crypt(dev_sched, iv, src, dst, n_blocks=None, stream=None) -> None:

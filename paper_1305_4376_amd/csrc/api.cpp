@@ -100,10 +100,12 @@ extern "C" int tdes_ecb_decrypt(const void *dev_sched, const void *in, void *out
 }
 
 extern "C" int tdes_ecb_chunked(const void *dev_sched, const void *in, void *out, uint64_t n_blocks,
-                                uint64_t chunk_blocks, int direction, void *stream) {
+                                uint64_t chunk_blocks, int direction, int variant, void *stream) {
     const int rc = check_buffers(dev_sched, in, out, n_blocks);
     if (rc != TDES_OK) return rc;
     if (direction != TDES_ENCRYPT && direction != TDES_DECRYPT) return TDES_ERR_ARG;
+    if (variant != TDES_VARIANT_AUTO && variant != TDES_VARIANT_TABLE && variant != TDES_VARIANT_BITSLICE)
+        return TDES_ERR_ARG;
     if (chunk_blocks == 0) return TDES_ERR_SIZE;
     const uint32_t *ks = static_cast<const uint32_t *>(dev_sched) + direction * tdes::kDirWords;
     const uint8_t *src = static_cast<const uint8_t *>(in);
@@ -111,7 +113,10 @@ extern "C" int tdes_ecb_chunked(const void *dev_sched, const void *in, void *out
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (uint64_t first = 0; first < n_blocks; first += chunk_blocks) {
         const uint64_t n = n_blocks - first < chunk_blocks ? n_blocks - first : chunk_blocks;
-        if (tdes::launch_bitslice(ks, src + 8 * first, dst + 8 * first, n, s) != hipSuccess) return TDES_ERR_HIP;
+        const hipError_t e = resolve_variant(variant, n) == TDES_VARIANT_BITSLICE
+                                 ? tdes::launch_bitslice(ks, src + 8 * first, dst + 8 * first, n, s)
+                                 : tdes::launch_table(ks, src + 8 * first, dst + 8 * first, n, s);
+        if (e != hipSuccess) return TDES_ERR_HIP;
     }
     return TDES_OK;
 }

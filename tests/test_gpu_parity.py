@@ -210,7 +210,8 @@ def test_host_resident_message(pinned):
     assert np.array_equal(dst.numpy() if pinned else dst, host)
 
 
-def test_chunked_launches_equal_one_launch():
+@pytest.mark.parametrize("variant", [td.TDES_VARIANT_AUTO, td.TDES_VARIANT_TABLE, td.TDES_VARIANT_BITSLICE])
+def test_chunked_launches_equal_one_launch(variant):
     """The paper's host loop (one launch per chunk, a short last chunk) gives the single launch's output."""
     n = 3 * 2048 * 5 + 777
     seed = inputs.DATA_SEED_BASE + 90
@@ -220,11 +221,11 @@ def test_chunked_launches_equal_one_launch():
     one = torch.empty_like(src)
     td.tdes_ecb_encrypt(sched, src, one)
     for chunk in (1, 100, 2048, 4096 + 8, n, 2 * n):
-        print(f"[parity] chunked chunk={chunk}", flush=True)
+        print(f"[parity] chunked variant={variant} chunk={chunk}", flush=True)
         out = torch.empty_like(src)
-        td.tdes_ecb_chunked(sched, src, out, chunk, n)
+        td.tdes_ecb_chunked(sched, src, out, chunk, n, variant=variant)
         torch.cuda.synchronize()
         assert torch.equal(out, one), chunk
     with pytest.raises(td.TdesError) as e:
-        td.tdes_ecb_chunked(sched, src, one, 0, n)
+        td.tdes_ecb_chunked(sched, src, one, 0, n, variant=variant)
     assert e.value.code == -4
