@@ -171,18 +171,24 @@ __device__ __forceinline__ void fold_fix(uint32_t (&h)[32], uint32_t w_in) {
     for (int q = 0; q < 32; q++) h[q] ^= key_mask(w, q);
 }
 
-// Stage `stage` (0..2) of EDE with folded masks: x holds L0 and y holds R0 on
-// entry, L16 and R16 on exit (both without folded keys).  fold: the direction's
-// folded words.
-__device__ __forceinline__ void des_stage_folded(uint32_t (&x)[32], uint32_t (&y)[32],
-                                                 const uint32_t *__restrict__ fold, int stage) {
-    fold_fix(y, fold[kFoldPre + stage]);
+// The 16 rounds of stage `stage` (0..2) with folded masks: x holds L0 and y
+// holds R0 on entry, L16 and R16 on exit; y enters folded with the stage's
+// first key and x leaves folded with its last.  fold: the direction's folded words.
+__device__ __forceinline__ void des_rounds_folded(uint32_t (&x)[32], uint32_t (&y)[32],
+                                                  const uint32_t *__restrict__ fold, int stage) {
     const uint32_t *ow = fold + kFoldOut + 16 * stage, *cw = fold + kFoldCorr + 16 * stage;
 #pragma unroll 1
     for (int r = 0; r < 16; r += 2) {
         feistel_folded(x, y, ow[r], cw[r]);
         feistel_folded(y, x, ow[r + 1], cw[r + 1]);
     }
+}
+
+// One whole stage, both halves without folded keys on entry and exit.
+__device__ __forceinline__ void des_stage_folded(uint32_t (&x)[32], uint32_t (&y)[32],
+                                                 const uint32_t *__restrict__ fold, int stage) {
+    fold_fix(y, fold[kFoldPre + stage]);
+    des_rounds_folded(x, y, fold, stage);
     fold_fix(x, fold[kFoldPost + stage]);
 }
 
@@ -222,9 +228,15 @@ __device__ __forceinline__ void tdes_32_blocks(uint32_t (&a)[32], uint32_t (&b)[
             }
         }
     } else {
-        des_stage_folded(l, r, ks + kFoldBase, 0);
-        des_stage_folded(r, l, ks + kFoldBase, 1);
-        des_stage_folded(l, r, ks + kFoldBase, 2);
+        // stage s ends reading the half that stage s + 1 reads first: one fix-up between them
+        const uint32_t *fold = ks + kFoldBase;
+        fold_fix(r, fold[kFoldPre + 0]);
+        des_rounds_folded(l, r, fold, 0);
+        fold_fix(l, fold[kFoldMid + 0]);
+        des_rounds_folded(r, l, fold, 1);
+        fold_fix(r, fold[kFoldMid + 1]);
+        des_rounds_folded(l, r, fold, 2);
+        fold_fix(l, fold[kFoldPost + 2]);
     }
     // Preoutput R16 || L16 = (r, l); FP is a renaming back to block bit planes.
 #pragma unroll

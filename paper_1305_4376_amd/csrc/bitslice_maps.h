@@ -80,12 +80,16 @@ constexpr UseMaps kUses = make_uses();
 //   [kFoldOut + r]   round r: bit q = (k[r-1] xor k[r+1]) at first[q], both within r's stage (else 0);
 //   [kFoldCorr + r]  round r: bit t = k[r] at first[e[second_pos[t]]] xor k[r] at second_pos[t];
 //   [kFoldPre + s]   stage s: bit q = k[16s] at first[q]       (folded into the half read first);
-//   [kFoldPost + s]  stage s: bit q = k[16s + 15] at first[q]  (removed from the half read last).
+//   [kFoldPost + s]  stage s: bit q = k[16s + 15] at first[q]  (removed from the half read last);
+//   [kFoldMid + s]   s = 0, 1: [kFoldPost + s] xor [kFoldPre + s + 1].  The half that stage s reads
+//                    last is the half that stage s + 1 reads first, so between two stages one pass
+//                    exchanges the two folded keys.
 constexpr int kFoldBase = 96;  // offset of the folded words in a direction's block
 constexpr int kFoldOut = 0;
 constexpr int kFoldCorr = 48;
 constexpr int kFoldPre = 96;
 constexpr int kFoldPost = 99;
-constexpr int kFoldWords = 102;
+constexpr int kFoldMid = 102;
+constexpr int kFoldWords = 104;
 
 }  // namespace tdes_bs

@@ -14,7 +14,7 @@ namespace tdes {
 constexpr int kRounds = 48;
 constexpr int kRoundWords = 2 * kRounds;
 constexpr int kDirWords = 200;
-static_assert(kRoundWords + 102 <= kDirWords && 2 * kDirWords * 4 == TDES_SCHED_BYTES, "schedule layout");
+static_assert(kRoundWords + 104 <= kDirWords && 2 * kDirWords * 4 == TDES_SCHED_BYTES, "schedule layout");
 
 // Per-device properties the launchers need (cached on first use).
 struct DeviceInfo {

@@ -90,6 +90,8 @@ void fold_words(const uint64_t sub[48], uint32_t *w) {
         w[tdes_bs::kFoldPre + st] = pre;
         w[tdes_bs::kFoldPost + st] = post;
     }
+    for (int st = 0; st < 2; st++)
+        w[tdes_bs::kFoldMid + st] = w[tdes_bs::kFoldPost + st] ^ w[tdes_bs::kFoldPre + st + 1];
 }
 
 // C0 and D0 of a key, for the weak-key test.

@@ -204,7 +204,7 @@ def test_folded_key_words_match_oracle_subkeys(keying):
         s1, s2, s3 = oracle.des_subkeys(k1), oracle.des_subkeys(k2), oracle.des_subkeys(k3)
         w = td.tdes_expand_key(k1, k2, k3).view("<u4")
         for d, order in enumerate((s1 + s2[::-1] + s3, s3[::-1] + s2 + s1[::-1])):
-            fold = w[DIR_WORDS * d + 96: DIR_WORDS * d + 96 + 102]
+            fold = w[DIR_WORDS * d + 96: DIR_WORDS * d + 96 + 104]
             for r in range(48):
                 i = r % 16
                 diff = (order[r - 1] if i > 0 else 0) ^ (order[r + 1] if i < 15 else 0)
@@ -214,6 +214,9 @@ def test_folded_key_words_match_oracle_subkeys(keying):
             for st in range(3):
                 assert int(fold[96 + st]) == sum(bit(order[16 * st], first[q]) << q for q in range(32))
                 assert int(fold[99 + st]) == sum(bit(order[16 * st + 15], first[q]) << q for q in range(32))
+            for st in range(2):   # between stages: remove stage st's last key, add stage st + 1's first
+                assert int(fold[102 + st]) == sum((bit(order[16 * st + 15], first[q]) ^
+                                                   bit(order[16 * st + 16], first[q])) << q for q in range(32))
 
 
 INC = os.path.join(os.path.dirname(SPEC), "sbox_circuits.inc")
