@@ -25,15 +25,25 @@ constexpr int kTileBlocks = 32 * kLanes;     // blocks per wave tile
 
 // One exchange stage of the transpose: for rows j and j + S (j & S == 0), swap the
 // bits of row j at positions i + S with those of row j + S at positions i, for the
-// positions i selected by M.
+// positions i selected by M.  On gfx950 v_bfi, v_perm and left shifts issue at half
+// the rate of v_bitop3 with vector-register operands, of adds and of right shifts
+// (measured), so the selects are v_bitop3 with the mask in a vector register and a
+// 1-bit left shift is an add.
 template <int S, uint32_t M>
 __device__ __forceinline__ void exchange_stage(uint32_t (&w)[32]) {
+    uint32_t m;
+    asm("v_mov_b32 %0, %1" : "=v"(m) : "i"(M));
 #pragma unroll
     for (int j = 0; j < 32; j++) {
         if (j & S) continue;
         const uint32_t a = w[j], b = w[j + S];
-        w[j] = (a & M) | ((b << S) & ~M);
-        w[j + S] = ((a >> S) & M) | (b & ~M);
+        uint32_t bs;
+        if constexpr (S == 1)
+            asm("v_add_u32 %0, %1, %1" : "=v"(bs) : "v"(b));            // b << 1 (the compiler would turn b + b into a shift)
+        else
+            bs = b << S;
+        w[j] = __builtin_amdgcn_bitop3_b32(a, bs, m, 0xE4);            // m ? a : bs
+        w[j + S] = __builtin_amdgcn_bitop3_b32(a >> S, b, m, 0xE4);    // m ? a >> S : b
     }
 }
 
