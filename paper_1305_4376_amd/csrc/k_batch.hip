@@ -13,11 +13,16 @@
 //                 remainders of many messages: every lane reads its own slot,
 //                 key and direction (key masks then come from vector registers).
 //
-// Work counter.  Each wave takes tickets until it draws one at or past the
-// tile count, so exactly n_tiles + (number of waves) tickets are drawn per
-// launch; the wave that draws the last one resets the counter to zero for the
-// next launch.  The kernel therefore needs no reset node and can be replayed
-// from a captured graph.  Every wave exits once the tiles run out.
+// Work assignment.  Wave w of the grid takes tile w first, with no atomic;
+// after each tile it draws its next one from a counter, as tile n_waves + the
+// counter's old value, and stops at the first draw at or past the tile count.
+// (All waves drawing their first tile from the counter at the same moment made
+// them queue on one atomic address at launch: 8% slower on whole-tile batches.)
+// Every wave that had a first tile makes exactly one failing draw, so exactly
+// n_tiles draws are made per launch and the one that returns n_tiles - 1 is the
+// last: that wave resets the counter to zero for the next launch.  The kernel
+// therefore needs no reset node and can be replayed from a captured graph.
+// Every wave exits once the tiles run out.
 #include <hip/hip_runtime.h>
 
 #include "batch_plan.h"
@@ -34,6 +39,17 @@ constexpr int kMaxThreads = 256;
 // lane tiles' per-lane load and store phases spill a few values to scratch.
 constexpr int kMinGroupsPerCU = 4;
 
+// A wave's tile after its first: n_waves + the counter's value (at or past n_tiles: none left).
+// Exactly n_tiles draws are made per launch (one failing draw per wave that had a first
+// tile), so the draw that returns n_tiles - 1 is the last one and resets the counter.
+__device__ __forceinline__ uint32_t next_ticket(uint32_t *counter, uint32_t n_tiles, uint32_t n_waves, uint32_t lane) {
+    uint32_t d = 0;
+    if (lane == 0) d = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    d = __builtin_amdgcn_readfirstlane(d);
+    if (d == n_tiles - 1 && lane == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return n_waves + d;
+}
+
 __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
@@ -47,15 +63,8 @@ __global__ __launch_bounds__(kMaxThreads, kMinGroupsPerCU) void tdes_batch_kerne
     const uint32_t n_tiles = hdr->n_tiles;
     const uint32_t n_slots = hdr->n_slots;
     const uint32_t n_waves = gridDim.x * (blockDim.x / kLanes);
-    for (;;) {
-        uint32_t ticket = 0;
-        if (lane == 0) ticket = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ticket = __builtin_amdgcn_readfirstlane(ticket);
-        if (ticket >= n_tiles) {
-            if (ticket == n_tiles + n_waves - 1 && lane == 0)
-                __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            break;
-        }
+    const uint32_t wave_id = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x / kLanes) + threadIdx.x / kLanes);
+    for (uint32_t ticket = wave_id; ticket < n_tiles; ticket = next_ticket(counter, n_tiles, n_waves, lane)) {
         const uint32_t t = __builtin_amdgcn_readfirstlane(tiles[ticket]);
         const uint32_t first_slot = t & ~tdes::kLaneTileBit;
         if (t & tdes::kLaneTileBit) {
