@@ -484,12 +484,13 @@ static void print_circuit(const circuit_t *C, const int outs[4], int cost) {
 }
 
 int main(int argc, char **argv) {
-    if (argc < 66) {
+    if (argc < 68) {
         fprintf(stderr, "usage: sbox_search SEED TRIALS BUDGET2 s0 .. s63 [WIDTH [IMPROVE]]\n"
                         "  IMPROVE > 0: large-neighbourhood search from a circuit on stdin, TRIALS iterations\n");
         return 2;
     }
-    const int width = argc > 67 ? atoi(argv[67]) : 1;  /* attempts per output, best kept */
+    /* argv[4..67]: the 64 table entries; then WIDTH and IMPROVE */
+    const int width = argc > 68 ? atoi(argv[68]) : 1;  /* attempts per output, best kept */
     rng_state ^= strtoull(argv[1], NULL, 0);
     int trials = atoi(argv[2]);
     int budget2 = atoi(argv[3]);
@@ -504,7 +505,7 @@ int main(int argc, char **argv) {
     circuit_t best;
     best.n = 6;
     int best_cost = 1 << 30, best_outs[4] = {0};
-    if (argc > 68 && atoi(argv[68]) > 0) return improve(target, trials, budget2, width);
+    if (argc > 69 && atoi(argv[69]) > 0) return improve(target, trials, budget2, width);
     for (int trial = 0; trial < trials; trial++) {
         g_allow_bidec = (int)(rnd() % 3 == 0);
         circuit_t C;
