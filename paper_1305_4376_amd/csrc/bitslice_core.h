@@ -287,7 +287,10 @@ __device__ __forceinline__ uint32_t be_lo_word(uint64_t v) { return __builtin_bs
 // 16-byte aligned.  Otherwise (n_valid < 2048, or buffers only 8-byte
 // aligned) each block is loaded and stored on its own, at the same
 // addresses, only if it is one of the first n_valid; lanes past the end
-// compute on zeros.
+// compute on zeros.  Whole-tile loads and stores are nontemporal: every block
+// is read and written once.
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+
 template <TileMode kMode, bool kFull>
 __device__ __forceinline__ void mode_tile(const uint32_t *__restrict__ ks, const uint8_t *tin, uint8_t *tout,
                                           uint32_t n_valid, uint32_t lane, uint64_t first_block, uint64_t iv) {
@@ -306,7 +309,7 @@ __device__ __forceinline__ void mode_tile(const uint32_t *__restrict__ ks, const
         for (int k = 0; k < 16; k++) {
             const uint8_t *p = tin + 1024 * k + 16 * lane;
             if (kFull) {
-                const uint4 v = *reinterpret_cast<const uint4 *>(p);
+                const v4u v = __builtin_nontemporal_load(reinterpret_cast<const v4u *>(p));
                 a[2 * k] = v.x; b[2 * k] = v.y; a[2 * k + 1] = v.z; b[2 * k + 1] = v.w;
             } else {
                 const uint32_t j = 128 * k + 2 * lane;
@@ -341,7 +344,8 @@ __device__ __forceinline__ void mode_tile(const uint32_t *__restrict__ ks, const
         }
         uint8_t *q = tout + 1024 * k + 16 * lane;
         if (kFull) {
-            *reinterpret_cast<uint4 *>(q) = make_uint4(a[2 * k], b[2 * k], a[2 * k + 1], b[2 * k + 1]);
+            v4u o = {a[2 * k], b[2 * k], a[2 * k + 1], b[2 * k + 1]};
+            __builtin_nontemporal_store(o, reinterpret_cast<v4u *>(q));
         } else {
             if (j < n_valid) *reinterpret_cast<uint2 *>(q) = make_uint2(a[2 * k], b[2 * k]);
             if (j + 1 < n_valid) *reinterpret_cast<uint2 *>(q + 8) = make_uint2(a[2 * k + 1], b[2 * k + 1]);
