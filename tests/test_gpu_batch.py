@@ -186,6 +186,37 @@ def test_batch_rejects_bad_jobs():
         td.tdes_ctx_destroy(ctx)
 
 
+def test_replays_with_more_tiles_than_waves():
+    """A small grid (one 64-thread workgroup per CU) takes most tiles from the work counter, so each
+    replay relies on the previous launch having left the counter at zero."""
+    keys, table = _table(16, 0xB21)
+    lengths = inputs.log_uniform_lengths(0xB22, 400, 40000)
+    jobs, buf, total = _layout(lengths, 0xB23)
+    jobs["sched_idx"] = np.arange(len(lengths)) % 16
+    ctx = td.tdes_ctx_create()
+    try:
+        td.tdes_ctx_set_tuning(ctx, 64, 1)
+        td.tdes_ecb_batch(ctx, jobs, table, 16, buf, td.TDES_BATCH_NO_GRAPH)
+        torch.cuda.synchronize()
+        info = td.tdes_ctx_get_info(ctx)
+        n_waves = torch.cuda.get_device_properties(0).multi_processor_count
+        assert info["tiles"] > 2 * n_waves, (info["tiles"], n_waves)
+        eager = buf[total:2 * total].clone()
+        _check_jobs(jobs, keys, buf, 0xB23, sample_per_job=32)
+        for rep in range(4):
+            print(f"[batch] replay {rep} with {info['tiles']} tiles on {n_waves} waves", flush=True)
+            buf[total:2 * total].zero_()
+            torch.cuda.synchronize()
+            if rep == 0:
+                td.tdes_ecb_batch(ctx, jobs, table, 16, buf, 0)
+            else:
+                td.tdes_ecb_batch_replay(ctx, td.TDES_BATCH_NO_GRAPH if rep == 3 else 0)
+            torch.cuda.synchronize()
+            assert torch.equal(buf[total:2 * total], eager), f"replay {rep}"
+    finally:
+        td.tdes_ctx_destroy(ctx)
+
+
 @pytest.mark.parametrize("shape", [(64, 1), (128, 2), (256, 1), (256, 6), (192, 3)])
 def test_batch_tuning_shapes(shape):
     keys, table = _table(5, 0xB31)
