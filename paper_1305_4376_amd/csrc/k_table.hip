@@ -151,13 +151,18 @@ __device__ __forceinline__ void tdes_two_blocks(uint32_t &w0, uint32_t &w1, uint
 template <bool kVec16>
 __global__ __launch_bounds__(kThreads) void tdes_table_kernel(const uint32_t *__restrict__ ks, const uint8_t *in,
                                                               uint8_t *out, uint64_t n_blocks) {
-    __shared__ uint32_t lds[8 * 64 * kCopies];
-    for (int i = threadIdx.x; i < 8 * 64 * kCopies; i += kThreads) {
-        // word i: region i / 4096 (boxes 2r, 2r+1), index (i / 64) % 64, half (i / 32) % 2, copy i % 32.
-        const int box = 2 * (i / 4096) + (i / 32) % 2;
-        lds[i] = g_sp.v[box][(i / 64) % 64];
+    __shared__ uint4 lds4[8 * 64 * kCopies / 4];
+    // The 32 copies of an entry are 128 contiguous bytes: each thread reads its entries once and
+    // writes them with 16-byte stores.
+    for (int e = threadIdx.x; e < 8 * 64; e += kThreads) {
+        const int box = e / 64, x = e % 64;
+        const uint32_t v = g_sp.v[box][x];
+        const int word = (box / 2) * 4096 + x * 64 + (box % 2) * 32;
+#pragma unroll
+        for (int k = 0; k < kCopies / 4; k++) lds4[word / 4 + k] = make_uint4(v, v, v, v);
     }
     __syncthreads();
+    const uint32_t *lds = reinterpret_cast<const uint32_t *>(lds4);
     const uint8_t *lbase = reinterpret_cast<const uint8_t *>(lds);
     const uint32_t lane4 = (threadIdx.x % kCopies) * 4;
 
