@@ -343,7 +343,7 @@ def tdes_server_run_trace(server: int, reqs: np.ndarray, arrival_s: np.ndarray) 
 
 
 def tdes_ecb_host(dev_sched, host_in, host_out, n_blocks=None, direction: int = TDES_ENCRYPT,
-                  chunk_blocks: int = 1 << 23, stream=None) -> None:
+                  chunk_blocks: int = 1 << 22, stream=None) -> None:
     """ECB over a host-resident message (numpy arrays or pinned tensors), copies overlapped in chunks."""
     n = _nblocks(host_in, n_blocks) if n_blocks is not None or hasattr(host_in, "numel") else np.asarray(host_in).nbytes // 8
     _check(load_library().tdes_ecb_host(_ptr(dev_sched), _ptr(host_in), _ptr(host_out), int(n), int(direction),
