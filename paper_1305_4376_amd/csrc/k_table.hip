@@ -152,14 +152,13 @@ template <bool kVec16>
 __global__ __launch_bounds__(kThreads) void tdes_table_kernel(const uint32_t *__restrict__ ks, const uint8_t *in,
                                                               uint8_t *out, uint64_t n_blocks) {
     __shared__ uint4 lds4[8 * 64 * kCopies / 4];
-    // The 32 copies of an entry are 128 contiguous bytes: each thread reads its entries once and
-    // writes them with 16-byte stores.
-    for (int e = threadIdx.x; e < 8 * 64; e += kThreads) {
-        const int box = e / 64, x = e % 64;
-        const uint32_t v = g_sp.v[box][x];
-        const int word = (box / 2) * 4096 + x * 64 + (box % 2) * 32;
+    // 16-byte stores of four copies each, consecutive lanes on consecutive 16 bytes (no bank
+    // conflicts); word w holds box 2 (w / 4096) + (w / 32) % 2, entry (w / 64) % 64.
 #pragma unroll
-        for (int k = 0; k < kCopies / 4; k++) lds4[word / 4 + k] = make_uint4(v, v, v, v);
+    for (int i = 0; i < 8 * 64 * kCopies / 4 / kThreads; i++) {
+        const int c = i * kThreads + threadIdx.x, w = 4 * c;
+        const uint32_t v = g_sp.v[2 * (w / 4096) + (w / 32) % 2][(w / 64) % 64];
+        lds4[c] = make_uint4(v, v, v, v);
     }
     __syncthreads();
     const uint32_t *lds = reinterpret_cast<const uint32_t *>(lds4);
