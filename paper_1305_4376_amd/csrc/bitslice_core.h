@@ -287,8 +287,8 @@ __device__ __forceinline__ uint32_t be_lo_word(uint64_t v) { return __builtin_bs
 // 16-byte aligned.  Otherwise (n_valid < 2048, or buffers only 8-byte
 // aligned) each block is loaded and stored on its own, at the same
 // addresses, only if it is one of the first n_valid; lanes past the end
-// compute on zeros.  Whole-tile loads and stores are nontemporal: every block
-// is read and written once.
+// compute on zeros.  Whole-tile loads and stores are nontemporal (every block
+// is read and written once), except CBC decryption's first read.
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
 template <TileMode kMode, bool kFull>
@@ -309,7 +309,9 @@ __device__ __forceinline__ void mode_tile(const uint32_t *__restrict__ ks, const
         for (int k = 0; k < 16; k++) {
             const uint8_t *p = tin + 1024 * k + 16 * lane;
             if (kFull) {
-                const v4u v = __builtin_nontemporal_load(reinterpret_cast<const v4u *>(p));
+                // CBC decryption reads its input a second time after the rounds: keep it cached
+                const v4u v = kMode == TileMode::kCbcDecrypt ? *reinterpret_cast<const v4u *>(p)
+                                                              : __builtin_nontemporal_load(reinterpret_cast<const v4u *>(p));
                 a[2 * k] = v.x; b[2 * k] = v.y; a[2 * k + 1] = v.z; b[2 * k + 1] = v.w;
             } else {
                 const uint32_t j = 128 * k + 2 * lane;
