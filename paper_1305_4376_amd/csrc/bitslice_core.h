@@ -288,7 +288,8 @@ __device__ __forceinline__ uint32_t be_lo_word(uint64_t v) { return __builtin_bs
 // aligned) each block is loaded and stored on its own, at the same
 // addresses, only if it is one of the first n_valid; lanes past the end
 // compute on zeros.  Whole-tile loads and stores are nontemporal (every block
-// is read and written once), except CBC decryption's first read.
+// is read and written once), except CBC decryption's first read, which is read
+// again after the rounds.
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
 template <TileMode kMode, bool kFull>
@@ -330,7 +331,7 @@ __device__ __forceinline__ void mode_tile(const uint32_t *__restrict__ ks, const
         const uint8_t *p = tin + 1024 * k + 16 * lane;
         if constexpr (kMode == TileMode::kCtr) {  // the keystream meets the data
             if (kFull) {
-                const uint4 v = *reinterpret_cast<const uint4 *>(p);
+                const v4u v = __builtin_nontemporal_load(reinterpret_cast<const v4u *>(p));
                 a[2 * k] ^= v.x; b[2 * k] ^= v.y; a[2 * k + 1] ^= v.z; b[2 * k + 1] ^= v.w;
             } else {
                 uint2 v0 = make_uint2(0, 0), v1 = make_uint2(0, 0);
