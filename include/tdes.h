@@ -217,11 +217,14 @@ typedef struct tdes_batch_info {
 #define TDES_BATCH_PER_MESSAGE 2u  /* baseline: one plain launch per message, automatic variant (no plan, no graph) */
 
 /*
- * Create a batch context on the current device (allocates ~256 bytes of device
- * memory and a stream; the plan buffers grow on demand).
- * Errors: TDES_ERR_NULL, TDES_ERR_HIP, TDES_ERR_NOMEM.
+ * Create a batch context on HIP device `device` (a negative value: the current
+ * device).  It allocates ~256 bytes of device memory and a stream there; the
+ * plan buffers grow on demand.  Every later call on the context makes that
+ * device current for its duration (and restores the caller's), so the stream
+ * passed to it must belong to that device.
+ * Errors: TDES_ERR_NULL, TDES_ERR_ARG (no such device), TDES_ERR_HIP, TDES_ERR_NOMEM.
  */
-int tdes_ctx_create(tdes_ctx **ctx);
+int tdes_ctx_create(tdes_ctx **ctx, int device);
 
 /* Destroy a context after its last batch has finished.  NULL is a no-op. */
 int tdes_ctx_destroy(tdes_ctx *ctx);

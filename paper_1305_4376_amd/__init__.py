@@ -100,7 +100,7 @@ def load_library():
         "tdes_cbc_decrypt": ([vp, vp, vp, vp, u64, vp], i32),
         "tdes_status_str": ([i32], ctypes.c_char_p),
         "tdes_fill_splitmix64": ([vp, u64, u64, u64, vp], i32),
-        "tdes_ctx_create": ([ctypes.POINTER(vp)], i32),
+        "tdes_ctx_create": ([ctypes.POINTER(vp), i32], i32),
         "tdes_ctx_destroy": ([vp], i32),
         "tdes_ecb_batch": ([vp, vp, u32, vp, u64, vp, u32, vp], i32),
         "tdes_ecb_batch_replay": ([vp, u32, vp], i32),
@@ -147,15 +147,49 @@ def _stream(stream, like=None):
     return torch.cuda.current_stream(dev).cuda_stream
 
 
+def _nbytes(x) -> int | None:
+    """Size in bytes of a torch tensor or numpy array (its data must be contiguous); None for raw addresses."""
+    if x is None or isinstance(x, int):
+        return None
+    if hasattr(x, "numel"):
+        if not x.is_contiguous():
+            raise ValueError("buffers must be contiguous")
+        return x.numel() * x.element_size()
+    if isinstance(x, np.ndarray):
+        if not x.flags["C_CONTIGUOUS"]:
+            raise ValueError("buffers must be contiguous")
+        return x.nbytes
+    return None
+
+
+def _need(x, nbytes: int, what: str) -> None:
+    """Raise before any C call if a sized buffer is smaller than the call would touch."""
+    have = _nbytes(x)
+    if have is not None and nbytes > have:
+        raise ValueError(f"{what}: the call touches {nbytes} bytes but the buffer holds {have}")
+
+
 def _nblocks(buf, n_blocks):
     if n_blocks is not None:
-        return int(n_blocks)
-    if hasattr(buf, "numel"):
-        nbytes = buf.numel() * buf.element_size()
+        n = int(n_blocks)
+        if n < 0:
+            raise ValueError("n_blocks must not be negative")
+        return n
+    nbytes = _nbytes(buf)
+    if nbytes is not None:
         if nbytes % 8:
             raise ValueError("buffer is not a whole number of 8-byte blocks")
         return nbytes // 8
     raise ValueError("n_blocks is required for raw addresses")
+
+
+def _message_args(dev_sched, src, dst, n_blocks):
+    """Block count of a one-message call, with every sized buffer checked against it."""
+    n = _nblocks(src, n_blocks)
+    _need(dev_sched, TDES_SCHED_BYTES, "schedule")
+    _need(src, 8 * n, "input")
+    _need(dst, 8 * n, "output")
+    return n
 
 
 def _check(rc: int, where: str):
@@ -187,13 +221,16 @@ def tdes_sched_upload(host, dev_table, count: int | None = None, stream=None) ->
         if h.size % TDES_SCHED_BYTES:
             raise ValueError(f"host schedules must be a multiple of {TDES_SCHED_BYTES} bytes")
         count = h.size // TDES_SCHED_BYTES
+    if int(count) * TDES_SCHED_BYTES > h.size:
+        raise ValueError(f"{count} schedules need {int(count) * TDES_SCHED_BYTES} host bytes, {h.size} given")
+    _need(dev_table, int(count) * TDES_SCHED_BYTES, "schedule table")
     _check(load_library().tdes_sched_upload(h.ctypes.data, int(count), _ptr(dev_table), _stream(stream, dev_table)),
            "tdes_sched_upload")
 
 
 def tdes_ecb_run(dev_sched, src, dst, n_blocks=None, direction: int = TDES_ENCRYPT,
                  variant: int = TDES_VARIANT_AUTO, stream=None) -> None:
-    n = _nblocks(src, n_blocks)
+    n = _message_args(dev_sched, src, dst, n_blocks)
     _check(load_library().tdes_ecb_run(_ptr(dev_sched), _ptr(src), _ptr(dst), n, int(direction), int(variant),
                                        _stream(stream, src)), "tdes_ecb_run")
 
@@ -208,46 +245,47 @@ def _iv_buffer(iv):
 def tdes_ecb_chunked(dev_sched, src, dst, chunk_blocks: int, n_blocks=None, direction: int = TDES_ENCRYPT,
                      variant: int = TDES_VARIANT_AUTO, stream=None) -> None:
     """The paper's host loop: one launch per chunk of chunk_blocks blocks."""
-    n = _nblocks(src, n_blocks)
+    n = _message_args(dev_sched, src, dst, n_blocks)
     _check(load_library().tdes_ecb_chunked(_ptr(dev_sched), _ptr(src), _ptr(dst), n, int(chunk_blocks),
                                            int(direction), int(variant), _stream(stream, src)), "tdes_ecb_chunked")
 
 
 def tdes_ctr_crypt(dev_sched, iv, src, dst, n_blocks=None, stream=None) -> None:
     """CTR mode (encrypt or decrypt): dst = src XOR EDE(iv + j)."""
-    n = _nblocks(src, n_blocks)
+    n = _message_args(dev_sched, src, dst, n_blocks)
     _check(load_library().tdes_ctr_crypt(_ptr(dev_sched), _iv_buffer(iv), _ptr(src), _ptr(dst), n,
                                          _stream(stream, src)), "tdes_ctr_crypt")
 
 
 def tdes_cbc_decrypt(dev_sched, iv, src, dst, n_blocks=None, stream=None) -> None:
     """CBC decryption: dst[j] = EDE^-1(src[j]) XOR src[j-1], src[-1] = iv; src and dst must not overlap."""
-    n = _nblocks(src, n_blocks)
+    n = _message_args(dev_sched, src, dst, n_blocks)
     _check(load_library().tdes_cbc_decrypt(_ptr(dev_sched), _iv_buffer(iv), _ptr(src), _ptr(dst), n,
                                            _stream(stream, src)), "tdes_cbc_decrypt")
 
 
 def tdes_ecb_encrypt(dev_sched, src, dst, n_blocks=None, stream=None) -> None:
-    n = _nblocks(src, n_blocks)
+    n = _message_args(dev_sched, src, dst, n_blocks)
     _check(load_library().tdes_ecb_encrypt(_ptr(dev_sched), _ptr(src), _ptr(dst), n, _stream(stream, src)),
            "tdes_ecb_encrypt")
 
 
 def tdes_ecb_decrypt(dev_sched, src, dst, n_blocks=None, stream=None) -> None:
-    n = _nblocks(src, n_blocks)
+    n = _message_args(dev_sched, src, dst, n_blocks)
     _check(load_library().tdes_ecb_decrypt(_ptr(dev_sched), _ptr(src), _ptr(dst), n, _stream(stream, src)),
            "tdes_ecb_decrypt")
 
 
 def tdes_fill_splitmix64(dev, n_words: int, seed: int, first: int = 0, stream=None) -> None:
+    _need(dev, 8 * int(n_words), "output")
     _check(load_library().tdes_fill_splitmix64(_ptr(dev), int(n_words), int(seed) & (2**64 - 1), int(first),
                                                _stream(stream, dev)), "tdes_fill_splitmix64")
 
 
-def tdes_ctx_create() -> int:
-    """A batch context on the current device (an opaque handle)."""
+def tdes_ctx_create(device: int = -1) -> int:
+    """A batch context on HIP device `device` (-1: the current device); an opaque handle."""
     h = ctypes.c_void_p()
-    _check(load_library().tdes_ctx_create(ctypes.byref(h)), "tdes_ctx_create")
+    _check(load_library().tdes_ctx_create(ctypes.byref(h), int(device)), "tdes_ctx_create")
     return h.value
 
 
@@ -259,6 +297,11 @@ def tdes_ecb_batch(ctx: int, jobs: np.ndarray, dev_sched_table, n_scheds: int, d
                    stream=None) -> None:
     """jobs: a JOB_DTYPE array (host).  Offsets are relative to dev_base."""
     j = np.ascontiguousarray(jobs, dtype=JOB_DTYPE)
+    _need(dev_sched_table, int(n_scheds) * TDES_SCHED_BYTES, "schedule table")
+    if j.size and _nbytes(dev_base) is not None:
+        ends = 8 * j["n_blocks"].astype(np.uint64)
+        reach = max(int((j["in_off"] + ends).max()), int((j["out_off"] + ends).max()))
+        _need(dev_base, reach, "batch base")
     _check(load_library().tdes_ecb_batch(ctx, j.ctypes.data, int(j.size), _ptr(dev_sched_table), int(n_scheds),
                                          _ptr(dev_base), int(flags), _stream(stream, dev_base)), "tdes_ecb_batch")
 
@@ -280,6 +323,7 @@ def tdes_ctx_get_info(ctx: int) -> dict:
 def tdes_server_create(dev_sched_table, n_scheds: int, budget_bytes: int, max_inflight: int = 2,
                        max_step_jobs: int = 4096, max_step_blocks: int = 1 << 26, keep_outputs: bool = False) -> int:
     """Start a serving engine over a resident schedule table; returns an opaque handle."""
+    _need(dev_sched_table, int(n_scheds) * TDES_SCHED_BYTES, "schedule table")
     cfg = _ServeConfig(int(budget_bytes), int(max_inflight), int(max_step_jobs), int(max_step_blocks),
                        int(bool(keep_outputs)), 0)
     h = ctypes.c_void_p()
@@ -345,6 +389,6 @@ def tdes_server_run_trace(server: int, reqs: np.ndarray, arrival_s: np.ndarray) 
 def tdes_ecb_host(dev_sched, host_in, host_out, n_blocks=None, direction: int = TDES_ENCRYPT,
                   chunk_blocks: int = 1 << 22, stream=None) -> None:
     """ECB over a host-resident message (numpy arrays or pinned tensors), copies overlapped in chunks."""
-    n = _nblocks(host_in, n_blocks) if n_blocks is not None or hasattr(host_in, "numel") else np.asarray(host_in).nbytes // 8
+    n = _message_args(dev_sched, host_in, host_out, n_blocks)
     _check(load_library().tdes_ecb_host(_ptr(dev_sched), _ptr(host_in), _ptr(host_out), int(n), int(direction),
                                         int(chunk_blocks), _stream(stream)), "tdes_ecb_host")

@@ -257,9 +257,15 @@ int launch_plan(tdes_ctx *c, const void *sched, uint8_t *base, bool use_graph, h
 
 }  // namespace
 
-extern "C" int tdes_ctx_create(tdes_ctx **out) {
+extern "C" int tdes_ctx_create(tdes_ctx **out, int device) {
     if (!out) return TDES_ERR_NULL;
     *out = nullptr;
+    int n_dev = 0;
+    if (hipGetDeviceCount(&n_dev) != hipSuccess) return TDES_ERR_HIP;
+    if (device >= n_dev) return TDES_ERR_ARG;
+    if (device < 0 && hipGetDevice(&device) != hipSuccess) return TDES_ERR_HIP;
+    tdes::DeviceGuard guard(device);
+    if (!guard.ok()) return TDES_ERR_HIP;
     tdes::DeviceInfo dinfo;
     if (tdes::device_info(&dinfo) != TDES_OK) return TDES_ERR_HIP;
     tdes_ctx *c = new (std::nothrow) tdes_ctx;
@@ -283,6 +289,7 @@ extern "C" int tdes_ctx_create(tdes_ctx **out) {
 
 extern "C" int tdes_ctx_destroy(tdes_ctx *c) {
     if (!c) return TDES_OK;
+    tdes::DeviceGuard guard(c->device);
     if (c->plan_done) (void)hipEventSynchronize(c->plan_done);
     if (c->staging_free) (void)hipEventSynchronize(c->staging_free);
     if (c->exec) (void)hipGraphExecDestroy(c->exec);
@@ -323,6 +330,8 @@ extern "C" int tdes_ecb_batch(tdes_ctx *c, const tdes_job *jobs, uint32_t n_jobs
     if (n_scheds == 0 || n_scheds > (1ull << 32) / (TDES_SCHED_BYTES / 4)) return TDES_ERR_SIZE;
     int rc = validate_jobs(jobs, n_jobs, n_scheds, reinterpret_cast<uintptr_t>(dev_base));
     if (rc != TDES_OK) return rc;
+    tdes::DeviceGuard guard(c->device);
+    if (!guard.ok()) return TDES_ERR_HIP;
     hipStream_t s = static_cast<hipStream_t>(stream);
     uint8_t *base = static_cast<uint8_t *>(dev_base);
     const uint32_t *table = static_cast<const uint32_t *>(dev_sched_table);
@@ -369,6 +378,8 @@ extern "C" int tdes_ecb_batch_replay(tdes_ctx *c, uint32_t flags, void *stream) 
     if (flags & ~TDES_BATCH_NO_GRAPH) return TDES_ERR_ARG;
     if (!c->have_plan) return TDES_ERR_STATE;
     if (c->last_tiles == 0) return TDES_OK;
+    tdes::DeviceGuard guard(c->device);
+    if (!guard.ok()) return TDES_ERR_HIP;
     hipStream_t s = static_cast<hipStream_t>(stream);
     // Order after the plan's upload and the previous launch, whichever streams they ran on.
     if (hipStreamWaitEvent(s, c->staging_free, 0) != hipSuccess || hipStreamWaitEvent(s, c->plan_done, 0) != hipSuccess)

@@ -23,6 +23,29 @@ struct DeviceInfo {
 };
 int device_info(DeviceInfo *info);
 
+// Makes `device` current for the lifetime of the guard and restores the
+// caller's device afterwards (no-op when it already is current).
+class DeviceGuard {
+  public:
+    explicit DeviceGuard(int device) {
+        ok_ = hipGetDevice(&prev_) == hipSuccess;
+        if (ok_ && prev_ != device) {
+            ok_ = hipSetDevice(device) == hipSuccess;
+            switched_ = ok_;
+        }
+    }
+    ~DeviceGuard() {
+        if (switched_) (void)hipSetDevice(prev_);
+    }
+    bool ok() const { return ok_; }
+    DeviceGuard(const DeviceGuard &) = delete;
+    DeviceGuard &operator=(const DeviceGuard &) = delete;
+
+  private:
+    int prev_ = 0;
+    bool ok_ = false, switched_ = false;
+};
+
 // Kernel launchers.  Arguments are already validated; n_blocks > 0.
 // `ks` points at the 96 words of one direction.
 hipError_t launch_table(const uint32_t *ks, const uint8_t *in, uint8_t *out, uint64_t n_blocks,

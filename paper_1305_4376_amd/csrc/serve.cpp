@@ -407,7 +407,7 @@ extern "C" int tdes_server_create(tdes_server **out, const tdes_serve_config *cf
     s->pool.init(s->cfg.budget_bytes);
     s->steps.resize(cfg->max_inflight);
     for (Step &st : s->steps) {
-        if (tdes_ctx_create(&st.ctx) != TDES_OK ||
+        if (tdes_ctx_create(&st.ctx, s->device) != TDES_OK ||
             hipStreamCreateWithFlags(&st.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&st.done, hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&st.fill_staged, hipEventDisableTiming) != hipSuccess) {

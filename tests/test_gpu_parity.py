@@ -211,21 +211,29 @@ def test_host_resident_message(pinned):
 
 
 @pytest.mark.parametrize("variant", [td.TDES_VARIANT_AUTO, td.TDES_VARIANT_TABLE, td.TDES_VARIANT_BITSLICE])
-def test_chunked_launches_equal_one_launch(variant):
-    """The paper's host loop (one launch per chunk, a short last chunk) gives the single launch's output."""
-    n = 3 * 2048 * 5 + 777
-    seed = inputs.DATA_SEED_BASE + 90
-    keys = inputs.key_triple(inputs.KEY_SEED_BASE + 90)
-    sched = _gpu.device_sched(*keys)
-    src = _gpu.device_message(seed, n)
-    one = torch.empty_like(src)
-    td.tdes_ecb_encrypt(sched, src, one)
-    for chunk in (1, 100, 2048, 4096 + 8, n, 2 * n):
-        print(f"[parity] chunked variant={variant} chunk={chunk}", flush=True)
-        out = torch.empty_like(src)
-        td.tdes_ecb_chunked(sched, src, out, chunk, n, variant=variant)
-        torch.cuda.synchronize()
-        assert torch.equal(out, one), chunk
-    with pytest.raises(td.TdesError) as e:
-        td.tdes_ecb_chunked(sched, src, one, 0, n, variant=variant)
-    assert e.value.code == -4
+def test_chunked_launches_match_oracle(variant):
+    """The paper's host loop (Listing 1.1: one launch per chunk), every block of both directions
+    against the oracle: chunk sizes from one block to past the message, a short last chunk, and the
+    paper's 131072 blocks per launch on a message that also spans a 2^20-block chunk (where the
+    automatic variant switches to the bitsliced kernel)."""
+    cases = [(3 * 2048 * 5 + 777, (1, 100, 2048, 4096 + 8, 3 * 2048 * 5 + 777, 2 * (3 * 2048 * 5 + 777))),
+             ((1 << 20) + 3 * 2048 + 777, (131072, 1 << 20))]
+    for ci, (n, chunks) in enumerate(cases):
+        seed = inputs.DATA_SEED_BASE + 90 + ci
+        keys = inputs.key_triple(inputs.KEY_SEED_BASE + 90 + ci)
+        sched = _gpu.device_sched(*keys)
+        host = inputs.message(seed, n)
+        src = _gpu.to_device(host)
+        want = {d: _gpu.oracle_on_blocks(keys, host, decrypt=d == td.TDES_DECRYPT) for d in DIRS}
+        for chunk in chunks:
+            for d in DIRS:
+                print(f"[parity] chunked variant={variant} n={n} chunk={chunk} dir={d}", flush=True)
+                out = torch.empty_like(src)
+                td.tdes_ecb_chunked(sched, src, out, chunk, n, direction=d, variant=variant)
+                torch.cuda.synchronize()
+                got = out.cpu().numpy()
+                assert np.array_equal(got, want[d]), \
+                    f"chunk {chunk}: first mismatch at block {np.argmax((got != want[d]).reshape(-1, 8).any(1))}"
+        with pytest.raises(td.TdesError) as e:
+            td.tdes_ecb_chunked(sched, src, src, 0, n, variant=variant)
+        assert e.value.code == -4

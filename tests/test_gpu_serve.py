@@ -2,7 +2,9 @@
 
 The pin: every request's output is ECB-EDE of its own payload under its own
 key (Abstract, Section II.A), the same bit for bit whether it runs alone or in
-a mix of overlapping requests, and equal to the oracle on sampled blocks.
+a mix of overlapping requests, and equal to the oracle on every block.  One
+test runs the serving workload's own shape (65536 resident triples, requests
+of 512 B .. 16 MiB, 2^24-block steps, three steps in flight, a 64 GiB budget).
 Admission is checked against the device-memory budget.
 """
 import ctypes
@@ -66,14 +68,18 @@ def _copy_dev(dst, src, nbytes):
     assert _hip.hipMemcpy(dst, src, nbytes, 3) == 0  # hipMemcpyDeviceToDevice
 
 
-def _check_oracle(keys, req, out, samples=32):
+def _check_oracle(keys, req, out):
+    """Every block of a request's output against the oracle on its payload (the request's SplitMix64 stream)."""
     n = int(req["n_blocks"])
-    idx = np.unique(np.concatenate([[0, n - 1], np.random.default_rng(int(req["seed"])).integers(0, n, samples)]))
     k = keys[req["key_id"]]
-    src = inputs.blocks_at(int(req["seed"]), idx)
+    src = inputs.message(int(req["seed"]), n)
     want = _gpu.oracle_on_blocks((k[:8].tobytes(), k[8:16].tobytes(), k[16:].tobytes()), src,
                                  decrypt=bool(req["direction"]))
-    assert np.array_equal(out.reshape(-1, 8)[idx].reshape(-1), want)
+    assert out.size == want.size
+    if not np.array_equal(out, want):
+        bad = np.flatnonzero((out != want).reshape(-1, 8).any(1))
+        raise AssertionError(f"request tag {int(req['user_tag'])} (key {int(req['key_id'])}, {n} blocks): "
+                             f"{bad.size} blocks differ from the oracle, first {bad[0]}")
 
 
 def test_alone_equals_in_the_mix(table):
@@ -107,7 +113,7 @@ def test_alone_equals_in_the_mix(table):
         td.tdes_server_destroy(server)
     for i in probe:
         assert np.array_equal(alone[i], mixed[i]), f"request {i} differs alone and in the mix"
-    for i in range(0, reqs.size, 7):
+    for i in range(reqs.size):
         _check_oracle(keys, reqs[i], mixed[i])
 
 
@@ -172,5 +178,63 @@ def test_host_payloads(table):
         k = keys[9]
         want = _gpu.oracle_on_blocks((k[:8].tobytes(), k[8:16].tobytes(), k[16:].tobytes()), host_in, decrypt=True)
         assert np.array_equal(host_out, want)
+    finally:
+        td.tdes_server_destroy(server)
+
+
+SERVE_KEYS = 65536
+
+
+def test_serving_workload_shape_every_block():
+    """The serving workload's shape: 65536 resident three-key triples (schedule offsets up to
+    ~100 MiB into the table), requests log-uniform from 64 to 2^21 blocks (512 B .. 16 MiB) including
+    one of exactly 2^21 blocks and key ids at the top of the table, 50/50 directions, a 64 GiB budget,
+    three steps in flight of at most 2^24 blocks, outputs kept on the device.  Every block of every
+    request is compared with the oracle, and 24 requests (the largest among them) are also run alone
+    and compared with their result in the mix."""
+    keys = inputs.key_triples(0x5E10, SERVE_KEYS)
+    host = np.concatenate([td.tdes_expand_key(k[:8].tobytes(), k[8:16].tobytes(), k[16:].tobytes()) for k in keys])
+    dev_table = torch.empty(host.size, dtype=torch.uint8, device=DEV)
+    td.tdes_sched_upload(host, dev_table)
+    del host
+    n = 96
+    rng = np.random.default_rng(0x5E11)
+    reqs = np.zeros(n, dtype=td.REQUEST_DTYPE)
+    u = rng.random(n)
+    reqs["n_blocks"] = np.floor(np.exp(np.log(64) + u * (np.log(2 ** 21) - np.log(64)))).astype(np.int64)
+    reqs["n_blocks"][[5, 60]] = [1 << 21, 64]
+    reqs["key_id"] = rng.integers(0, SERVE_KEYS, n)
+    reqs["key_id"][[1, 2, 3, 5, 90]] = [SERVE_KEYS - 1, SERVE_KEYS - 2, 0, SERVE_KEYS - 1, SERVE_KEYS - 3]
+    reqs["direction"] = rng.integers(0, 2, n)
+    reqs["seed"] = 0x5E120000 + np.arange(n)
+    reqs["user_tag"] = np.arange(n)
+    probe = sorted(set([5, 1, 2, 3, 60, 90] + rng.choice(n, 24, replace=False).tolist()))[:24]
+    if 5 not in probe:
+        probe[-1] = 5
+    print(f"[serve] {n} requests, {int(reqs['n_blocks'].sum())} blocks, mixed run", flush=True)
+    server = td.tdes_server_create(dev_table, SERVE_KEYS, 64 << 30, max_inflight=3, max_step_jobs=4096,
+                                   max_step_blocks=1 << 24, keep_outputs=True)
+    try:
+        arrival = np.cumsum(rng.exponential(0.0002, n))
+        done = td.tdes_server_run_trace(server, reqs, arrival)
+        assert (done["status"] == 0).all()
+        stats = td.tdes_server_stats(server)
+        assert stats["completed"] == n and stats["steps"] > 1
+        mixed = _outputs_by_tag(server, done, reqs)
+        assert td.tdes_server_stats(server)["pool_bytes_in_use"] == 0
+    finally:
+        td.tdes_server_destroy(server)
+    print(f"[serve] oracle on every block ({stats['steps']} steps)", flush=True)
+    for i in range(n):
+        _check_oracle(keys, reqs[i], mixed[i])
+    print(f"[serve] {len(probe)} requests alone", flush=True)
+    server = td.tdes_server_create(dev_table, SERVE_KEYS, 64 << 30, max_inflight=3, max_step_jobs=4096,
+                                   max_step_blocks=1 << 24, keep_outputs=True)
+    try:
+        for i in probe:
+            td.tdes_server_submit(server, reqs[i])
+            td.tdes_server_wait_idle(server, 120)
+            alone = _outputs_by_tag(server, td.tdes_server_poll(server), reqs)
+            assert np.array_equal(alone[i], mixed[i]), f"request {i} differs alone and in the mix"
     finally:
         td.tdes_server_destroy(server)

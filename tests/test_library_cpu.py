@@ -275,3 +275,56 @@ def test_generated_sbox_circuits_equal_oracle_tables():
         assert results[(f"sbox{b}", 0)] == want, b
         assert results[(f"sbox{b}_m", 0)] == want, b
         assert results[(f"sbox{b}_m", full)] == [w ^ full for w in want], b
+
+
+def test_binding_checks_buffer_sizes_before_the_c_call():
+    """Sized buffers (tensors, arrays) smaller than a call would touch raise ValueError in the binding,
+    before anything reaches the library or a device (host arrays stand in for device tensors here)."""
+    sched = np.zeros(td.TDES_SCHED_BYTES, np.uint8)
+    a, b = np.zeros(64, np.uint8), np.zeros(56, np.uint8)
+    with pytest.raises(ValueError, match="output"):
+        td.tdes_ecb_run(sched, a, b)                       # 8 blocks in, room for 7 out
+    with pytest.raises(ValueError, match="input"):
+        td.tdes_ecb_encrypt(sched, b, a, n_blocks=8)        # explicit count past the input
+    with pytest.raises(ValueError, match="schedule"):
+        td.tdes_ecb_decrypt(sched[:800], a, a)
+    with pytest.raises(ValueError, match="output"):
+        td.tdes_ctr_crypt(sched, b"\0" * 8, a, b)
+    with pytest.raises(ValueError, match="output"):
+        td.tdes_cbc_decrypt(sched, b"\0" * 8, a, b)
+    with pytest.raises(ValueError, match="output"):
+        td.tdes_ecb_chunked(sched, a, b, 2)
+    with pytest.raises(ValueError, match="output"):
+        td.tdes_ecb_host(sched, a, b)
+    with pytest.raises(ValueError, match="output"):
+        td.tdes_fill_splitmix64(b, 8, 1)
+    with pytest.raises(ValueError, match="8-byte"):
+        td.tdes_ecb_run(sched, a[:60], a[:60])
+    with pytest.raises(ValueError, match="negative"):
+        td.tdes_ecb_run(sched, a, a, n_blocks=-1)
+    with pytest.raises(ValueError, match="contiguous"):
+        td.tdes_ecb_run(sched, a.reshape(8, 8)[:, :4], a)
+    with pytest.raises(ValueError, match="schedule table"):
+        td.tdes_sched_upload(np.zeros(2 * td.TDES_SCHED_BYTES, np.uint8), sched)
+    with pytest.raises(ValueError, match="host bytes"):
+        td.tdes_sched_upload(sched, np.zeros(2 * td.TDES_SCHED_BYTES, np.uint8), count=2)
+    jobs = np.zeros(2, dtype=td.JOB_DTYPE)
+    jobs["n_blocks"] = 4
+    jobs["in_off"] = [0, 32]
+    jobs["out_off"] = [64, 96]                             # the second output ends at byte 128
+    with pytest.raises(ValueError, match="batch base"):
+        td.tdes_ecb_batch(0, jobs, sched, 1, np.zeros(120, np.uint8))
+    with pytest.raises(ValueError, match="schedule table"):
+        td.tdes_ecb_batch(0, jobs, sched, 2, np.zeros(128, np.uint8))
+    with pytest.raises(ValueError, match="schedule table"):
+        td.tdes_server_create(sched, 2, 1 << 20)
+
+
+def test_ctx_create_rejects_a_missing_device():
+    """tdes_ctx_create takes a device; one past the device count is an argument error (no GPU here:
+    the count is 0, so any non-negative device is missing)."""
+    lib = td.load_library()
+    h = ctypes.c_void_p()
+    rc = lib.tdes_ctx_create(ctypes.byref(h), 1 << 20)
+    assert rc in (-7, -8) and not h.value     # -8 where the runtime cannot count devices at all
+    assert lib.tdes_ctx_create(None, 0) == -1
