@@ -1,7 +1,7 @@
 """Generate the bitsliced kernel's S-box circuits (csrc/sbox_circuits.inc).
 
     python -m paper_1305_4376_amd.gen.gen_sbox [--search TRIALS] [--budget N] [--seeds K] [--width W]
-                                               [--polish ITERATIONS] [--lns ITERATIONS]
+                                               [--lns ITERATIONS]
 
 Each of the eight DES S-boxes (read from csrc/des_spec.h, the table the other
 kernel uses too) becomes a function of six bit planes that XORs its four
@@ -13,9 +13,7 @@ The circuits come from sbox_search.c (a randomized decomposition search
 written for this purpose; see that file).  The chosen ones are stored in
 sbox_circuits.txt; with --search the search runs again and a circuit replaces
 the stored one only if it has fewer gates (then a lower cost).  --lns runs
-the search's large-neighbourhood mode from each stored circuit.  --polish runs
-two local improvers on the stored circuits: sbox_cgp.c (evolution with
-resubstitution) and sbox_resyn.c (resynthesis of fanout-free cones).  Every
+the search's large-neighbourhood mode from each stored circuit.  Every
 circuit is checked on all 64 inputs before any code is written.
 """
 from __future__ import annotations
@@ -34,8 +32,6 @@ SPEC = os.path.join(PKG, "csrc", "des_spec.h")
 OUT_INC = os.path.join(PKG, "csrc", "sbox_circuits.inc")
 STORE = os.path.join(HERE, "sbox_circuits.txt")
 SEARCH_SRC = os.path.join(HERE, "sbox_search.c")
-CGP_SRC = os.path.join(HERE, "sbox_cgp.c")
-RESYN_SRC = os.path.join(HERE, "sbox_resyn.c")
 
 MASK64 = (1 << 64) - 1
 
@@ -163,13 +159,13 @@ def last_circuit(text: str) -> Circuit | None:
     return Circuit.parse(blocks[-1]) if blocks else None
 
 
-def run_polish(exe, args, tab, circuit: Circuit, last: bool = False) -> Circuit | None:
-    """Feed a stored circuit to an improver; return its (last printed) output circuit, or None."""
+def run_from(exe, args, tab, circuit: Circuit) -> Circuit | None:
+    """Feed a stored circuit to the search's large-neighbourhood mode; return the last circuit it printed, or None."""
     res = subprocess.run([exe] + [str(a) for a in args] + [str(v) for v in tab], input=circuit.dump(),
                          stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, text=True)
     if res.returncode != 0 or "\n" not in res.stdout:
         return None
-    return last_circuit(res.stdout) if last else Circuit.parse(res.stdout.split("\n", 1)[1])
+    return last_circuit(res.stdout)
 
 
 def emit(circuits: dict[int, Circuit], boxes) -> str:
@@ -234,7 +230,6 @@ def main():
     ap.add_argument("--budget", type=int, default=200000)
     ap.add_argument("--seeds", type=int, default=8)
     ap.add_argument("--width", type=int, default=1, help="search: attempts per output, best kept")
-    ap.add_argument("--polish", type=int, default=0, help="iterations of the local improvers (0: none)")
     ap.add_argument("--lns", type=int, default=0, help="iterations of the search's large-neighbourhood mode (0: none)")
     ap.add_argument("--boxes", default="1,2,3,4,5,6,7,8")
     ap.add_argument("--store", default=STORE, help="circuit store to read and update")
@@ -267,23 +262,12 @@ def main():
         exe = build_tool(SEARCH_SRC)
         jobs = [(b, s) for b in todo if b in circuits for s in range(args.seeds)]
         with ThreadPoolExecutor(max_workers=workers) as pool:
-            results = list(pool.map(lambda bs: (bs[0], run_polish(
+            results = list(pool.map(lambda bs: (bs[0], run_from(
                 exe, [7000 * bs[0] + bs[1] + 1, args.lns, args.budget], boxes[bs[0]] + [max(args.width, 1), 1],
-                circuits[bs[0]], last=True)), jobs))
+                circuits[bs[0]])), jobs))
         for b, c in results:
             accept(b, c, "large-neighbourhood search")
-    if args.polish:
-        cgp, resyn = build_tool(CGP_SRC), build_tool(RESYN_SRC)
-        jobs = [(b, s) for b in todo if b in circuits for s in range(args.seeds)]
-        with ThreadPoolExecutor(max_workers=workers) as pool:
-            results = list(pool.map(lambda bs: (bs[0], run_polish(cgp, [bs[1] + 1, args.polish, 8], boxes[bs[0]],
-                                                                  circuits[bs[0]])), jobs))
-        for b, c in results:
-            accept(b, c, "evolution")
-        for b in todo:
-            if b in circuits:
-                accept(b, run_polish(resyn, [1, 8], boxes[b], circuits[b]), "cone resynthesis")
-    if args.search or args.polish:
+    if args.search or args.lns:
         save_store(circuits, args.store)
     missing = [b + 1 for b in range(8) if b not in circuits]
     if missing:
