@@ -261,6 +261,44 @@ int tdes_ecb_batch_replay(tdes_ctx *ctx, uint32_t flags, void *stream);
 int tdes_ctx_set_tuning(tdes_ctx *ctx, uint32_t threads, uint32_t groups_per_cu);
 int tdes_ctx_get_info(const tdes_ctx *ctx, tdes_batch_info *info);
 
+/* ---- batched ECB without allocation ---- */
+
+/* Most jobs one tdes_ecb_batch_static call takes. */
+#define TDES_STATIC_MAX_JOBS 65536
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as tdes_ecb_batch on the same jobs, with no context, no host
+ * planning, no allocation and no host-device copy.  Its only working memory
+ * is a fixed array of about 260 KiB per GPU inside the library (the job
+ * plan: one word per job, a tile counter), set up on the first call on each
+ * device and held until the process ends.
+ *   dev_jobs: device, n_jobs tdes_job entries (8-byte aligned), read by the
+ *             kernels; n_jobs at most TDES_STATIC_MAX_JOBS, 0 enqueues nothing.
+ *   dev_sched_table: device, n_scheds schedules written by tdes_sched_upload.
+ *   dev_base, base_bytes: device buffer (8-byte aligned) holding every input
+ *             and output; offsets are relative to it.
+ *   dev_rejected: device, one uint32 (may be NULL): receives the number of
+ *             jobs the kernels refused -- a direction other than
+ *             TDES_ENCRYPT/TDES_DECRYPT, a schedule index >= n_scheds, more
+ *             than 2^40 blocks, an offset that is not a multiple of 8, input
+ *             or output reaching past base_bytes, or input and output sharing
+ *             bytes without being equal.  A refused job's output is not
+ *             written.  If the call's wave tiles (2048 blocks each, per job
+ *             rounded up) total 2^31 or more, every job is refused.
+ * Runs on the current device, on `stream` (which must belong to it): a plan
+ * launch, then the cipher launch.  Every call on one GPU uses that GPU's one
+ * array, so calls whose launches may overlap on the same GPU race: order
+ * them (one stream, or events).  As with tdes_ecb_batch, no message may
+ * write bytes another message of the call reads or writes (not checked here).
+ * Errors (synchronous, nothing enqueued): TDES_ERR_NULL, TDES_ERR_ALIGN,
+ * TDES_ERR_SIZE (n_jobs or n_scheds out of range), TDES_ERR_ARG (device
+ * index of 64 or more), TDES_ERR_HIP.
+ */
+int tdes_ecb_batch_static(const tdes_job *dev_jobs, uint32_t n_jobs, const void *dev_sched_table, uint64_t n_scheds,
+                          void *dev_base, uint64_t base_bytes, uint32_t *dev_rejected, void *stream);
+
 /* ---- serving: continuous batching of requests under resident keys ---- */
 
 /* A request.  Its input is n_blocks * 8 bytes: copied from host_in when that

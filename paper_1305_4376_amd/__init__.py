@@ -24,7 +24,7 @@ __all__ = [
     "REQUEST_DTYPE", "COMPLETION_DTYPE", "tdes_server_create", "tdes_server_destroy", "tdes_server_now",
     "tdes_server_submit", "tdes_server_cancel", "tdes_server_poll", "tdes_server_wait_idle",
     "tdes_server_release", "tdes_server_stats", "tdes_server_run_trace", "tdes_ecb_host",
-    "tdes_ctr_crypt", "tdes_cbc_decrypt", "tdes_ecb_chunked",
+    "tdes_ctr_crypt", "tdes_cbc_decrypt", "tdes_ecb_chunked", "TDES_STATIC_MAX_JOBS", "tdes_ecb_batch_static",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtdes.so")
@@ -35,6 +35,7 @@ TDES_CHECK_PARITY, TDES_REJECT_WEAK = 1, 2
 TDES_VARIANT_AUTO, TDES_VARIANT_TABLE, TDES_VARIANT_BITSLICE = 0, 1, 2
 TDES_SCHED_BYTES = 1600
 TDES_BATCH_NO_GRAPH, TDES_BATCH_PER_MESSAGE = 1, 2
+TDES_STATIC_MAX_JOBS = 65536
 
 # struct tdes_job (include/tdes.h): 32 bytes.
 JOB_DTYPE = np.dtype([("in_off", "<u8"), ("out_off", "<u8"), ("n_blocks", "<u8"), ("sched_idx", "<u4"),
@@ -104,6 +105,7 @@ def load_library():
         "tdes_ctx_destroy": ([vp], i32),
         "tdes_ecb_batch": ([vp, vp, u32, vp, u64, vp, u32, vp], i32),
         "tdes_ecb_batch_replay": ([vp, u32, vp], i32),
+        "tdes_ecb_batch_static": ([vp, u32, vp, u64, vp, u64, vp, vp], i32),
         "tdes_ctx_set_tuning": ([vp, u32, u32], i32),
         "tdes_ctx_get_info": ([vp, ctypes.POINTER(_BatchInfo)], i32),
         "tdes_server_create": ([ctypes.POINTER(vp), ctypes.POINTER(_ServeConfig), vp, u64], i32),
@@ -304,6 +306,24 @@ def tdes_ecb_batch(ctx: int, jobs: np.ndarray, dev_sched_table, n_scheds: int, d
         _need(dev_base, reach, "batch base")
     _check(load_library().tdes_ecb_batch(ctx, j.ctypes.data, int(j.size), _ptr(dev_sched_table), int(n_scheds),
                                          _ptr(dev_base), int(flags), _stream(stream, dev_base)), "tdes_ecb_batch")
+
+
+def tdes_ecb_batch_static(dev_jobs, n_jobs: int, dev_sched_table, n_scheds: int, dev_base, base_bytes=None,
+                          dev_rejected=None, stream=None) -> None:
+    """The allocation-free batch: dev_jobs is a device buffer of n_jobs JOB_DTYPE records; base_bytes
+    defaults to dev_base's size; dev_rejected (device, one uint32, optional) receives the refused-job count."""
+    _need(dev_jobs, int(n_jobs) * JOB_DTYPE.itemsize, "job table")
+    _need(dev_sched_table, int(n_scheds) * TDES_SCHED_BYTES, "schedule table")
+    _need(dev_rejected, 4, "rejected count")
+    have = _nbytes(dev_base)
+    if base_bytes is None:
+        if have is None:
+            raise ValueError("base_bytes is required for a raw base address")
+        base_bytes = have
+    _need(dev_base, int(base_bytes), "batch base")
+    _check(load_library().tdes_ecb_batch_static(_ptr(dev_jobs), int(n_jobs), _ptr(dev_sched_table), int(n_scheds),
+                                                _ptr(dev_base), int(base_bytes), _ptr(dev_rejected),
+                                                _stream(stream, dev_base)), "tdes_ecb_batch_static")
 
 
 def tdes_ecb_batch_replay(ctx: int, flags: int = 0, stream=None) -> None:
