@@ -51,11 +51,19 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--cpu-sample-blocks", type=int, default=1 << 23)
+    ap.add_argument("--cpu-one-thread-blocks", type=int, default=1 << 20)
     ap.add_argument("--serve-seconds", type=float, default=1.0, help="trace length per offered load")
     ap.add_argument("--no-host-path", action="store_true")
     ap.add_argument("--no-paper-ablation", action="store_true",
                     help="skip the paper's launch scheme: a 512 MiB message cut into launches of "
                          "128 .. 2^26 blocks (the analogue of Table II)")
+    ap.add_argument("--plain-only", action="store_true",
+                    help="only the timed encrypt + decrypt steps of the 1 GiB message (for profiling them alone)")
+    ap.add_argument("--no-c1", action="store_true", help="skip the 1 MiB message row")
+    ap.add_argument("--c1-only", action="store_true", help="only the 1 MiB message row (for profiling it alone)")
+    ap.add_argument("--tuning-cache", default=None,
+                    help="also record the batch and serving tunings chosen here in this autotuner cache file")
+    ap.add_argument("--no-c3", action="store_true", help="skip the keying x size x direction sweep")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 1 GiB elementwise XOR kernel (1 GiB read + 1 GiB written), the known-size "
                          "reference that scales the profiler's FETCH_SIZE / WRITE_SIZE counters")
@@ -122,7 +130,7 @@ def key_table(td, torch, inputs, seed, count, dev):
     return table
 
 
-def bench_batched(td, torch, inputs, dev, reps=10):
+def bench_batched(td, torch, inputs, dev, reps=10, cache=None):
     """C4: 4096 messages, log-uniform 1..131072 blocks, own three-key triple each, encrypt."""
     import numpy as np
     n_msgs = 4096
@@ -139,7 +147,7 @@ def bench_batched(td, torch, inputs, dev, reps=10):
     from paper_1305_4376_amd import autotune
     ctx = td.tdes_ctx_create()
     try:
-        tuned = autotune.tune_batch(ctx, jobs, table, n_msgs, buf, reps=3, path=None)
+        tuned = autotune.tune_batch(ctx, jobs, table, n_msgs, buf, reps=3, path=cache)
 
         def timed(fn):
             fn()
@@ -170,15 +178,17 @@ def bench_batched(td, torch, inputs, dev, reps=10):
         "identical_to_per_message": same,
         "tiles": info["tiles"], "lane_tiles": info["lane_tiles"],
         "padding_frac": round(info["padded_blocks"] / info["blocks"] - 1, 4),
-        "launch_shape": [info["threads"], info["groups_per_cu"]],
-        "autotune_ms": {f"{th}x{g}": t for t, th, g in tuned["candidates"][:6]},
-    }, total / t_replay
+        "tuning": {k: info[k] for k in ("threads", "groups_per_cu", "wave_remainder", "tiles_per_draw")},
+        "autotune_best_ms": {"x".join(str(v) for v in c[1:]): c[0] for c in tuned["candidates"][:6]},
+        "autotune_candidates": len(tuned["candidates"]),
+    }, total / t_replay, tuple(info[k] for k in ("threads", "groups_per_cu", "wave_remainder", "tiles_per_draw"))
 
 
-def bench_serving(td, torch, inputs, dev, batch_capacity_bps, seconds):
+def bench_serving(td, torch, inputs, dev, batch_capacity_bps, seconds, tuning=None, cache=None):
     """C5: Poisson arrivals, sizes log-uniform 512 B .. 16 MiB, 50/50 directions, 65536 resident triples,
-    64 GiB admission budget.  The server's own capacity is measured first (every request of a trace
-    arriving at once); the offered loads are 0.5 / 0.8 / 0.95 of it."""
+    64 GiB admission budget.  The batch shape of the server's steps is chosen by its saturated
+    throughput (every request of a trace arriving at once).  Offered loads: 0.5 / 0.8 / 0.95 of the batched workload's capacity (graph
+    replay), and the same fractions of the server's own saturated throughput."""
     import numpy as np
     n_keys = 65536
     table = key_table(td, torch, inputs, inputs.KEY_SEED_BASE + 5, n_keys, dev)
@@ -195,9 +205,9 @@ def bench_serving(td, torch, inputs, dev, batch_capacity_bps, seconds):
         arrival = np.cumsum(rng.exponential(1.0 / lam, n)) if lam else np.zeros(n)
         return reqs, arrival
 
-    def run(reqs, arrival):
+    def run(reqs, arrival, shape=None):
         server = td.tdes_server_create(table, n_keys, 64 << 30, max_inflight=3, max_step_jobs=4096,
-                                       max_step_blocks=1 << 24)
+                                       max_step_blocks=1 << 24, tuning=shape)
         try:
             # Warm-up: the first 5% of the trace (graph captures, plan buffers, first allocations), not measured.
             n_warm = max(200, len(reqs) // 20)
@@ -210,27 +220,48 @@ def bench_serving(td, torch, inputs, dev, batch_capacity_bps, seconds):
         ok = done["status"] == 0
         lat = (done["t_complete"] - done["t_arrival"])[ok]
         span = done["t_complete"].max() - done["t_arrival"].min()
+        wait = (done["t_admit"] - done["t_arrival"])[ok]
+        half = len(lat) // 2
         return {"requests": len(reqs), "delivered_gbs": round(float(reqs["n_blocks"][ok].sum() * 8) / span / 1e9, 2),
                 "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
                 "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                # queue growth: admission wait in the second half of the trace against the first
+                "admit_wait_ms_first_half": round(float(np.mean(wait[:half])) * 1e3, 3),
+                "admit_wait_ms_second_half": round(float(np.mean(wait[half:])) * 1e3, 3),
                 "failed": int((~ok).sum()), "steps": stats["steps"],
                 "peak_pool_gib": round(stats["peak_pool_bytes"] / 2 ** 30, 3)}
 
-    # Saturation: 20000 requests (about 31 GB of payload) all arriving at t = 0.
-    sat = run(*trace(0x5E50, 20000, 0.0))
+    # Saturation: 20000 requests (about 31 GB of payload) all arriving at t = 0, for each batch shape
+    # of the server's steps (the library's default and the one tuned on the batched workload); the
+    # fastest is kept for the loads.
+    from paper_1305_4376_amd import autotune
+    sat_trace = trace(0x5E50, 20000, 0.0)
+    candidates = {}
+
+    def saturated(sh):
+        candidates[sh] = run(*sat_trace, shape=sh)
+        return candidates[sh]["delivered_gbs"]
+    shape = autotune.tune_serving(saturated, [None] + ([tuple(tuning)] if tuning else []), 1 << 24,
+                                  path=cache)["shape"]
+    sat = candidates[shape]
     capacity_bps = sat["delivered_gbs"] * 1e9
-    results = []
-    for li, load in enumerate((0.5, 0.8, 0.95)):
-        lam = load * capacity_bps / mean_bytes
-        n = int(max(2000, min(400000, lam * seconds)))
-        r = run(*trace(0x5E5E + li, n, lam))
-        results.append({"load": load, "offered_gbs": round(lam * mean_bytes / 1e9, 2), **r})
+    by_batch, by_server = [], []
+    for rows, base_bps, tag in ((by_batch, batch_capacity_bps, 0), (by_server, capacity_bps, 8)):
+        for li, load in enumerate((0.5, 0.8, 0.95)):
+            lam = load * base_bps / mean_bytes
+            n = int(max(2000, min(400000, lam * seconds)))
+            r = run(*trace(0x5E5E + tag + li, n, lam), shape=shape)
+            rows.append({"load": load, "offered_gbs": round(lam * mean_bytes / 1e9, 2), **r})
     return {"workload": "Poisson arrivals, 512 B..16 MiB log-uniform, 50/50 encrypt/decrypt, 65536 resident "
                         "3-key triples, 64 GiB budget, payloads generated on the device at admission; latency = "
-                        "host-observed completion - scheduled arrival; each trace after a warm-up of 5% of it; "
-                        "loads relative to the server's saturated throughput",
+                        "host-observed completion - scheduled arrival; each trace after a warm-up of 5% of it",
+            "tuning": list(shape) if shape else "default",
+            "saturated_gbs_by_shape": {("x".join(map(str, sh)) if sh else "default"): r["delivered_gbs"]
+                                       for sh, r in candidates.items()},
             "capacity_gbs": round(capacity_bps / 1e9, 2), "batch_capacity_gbs": round(batch_capacity_bps / 1e9, 2),
-            "saturation": sat, "loads": results}
+            "saturation": sat,
+            "loads": by_batch, "loads_basis": "fractions of the batched workload's capacity (graph replay)",
+            "loads_vs_server": by_server, "loads_vs_server_basis": "fractions of the server's saturated throughput"}
 
 
 def bench_host_path(td, torch, sched, dev, reps=3):
@@ -305,7 +336,101 @@ def bench_paper_scheme(td, torch, sched, dev):
             "rows": rows}
 
 
-def cpu_baseline(sample_blocks):
+def time_launches(torch, fn, reps, warmup=3):
+    """Mean duration of `fn` (one or more launches on torch's current stream) from HIP events recorded
+    on that stream around each call, in seconds."""
+    for _ in range(warmup):
+        fn()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    return sum(a.elapsed_time(b) for a, b in ev) / reps / 1e3
+
+
+def bench_c1(td, torch, inputs, dev, ops_per_block, reps=200):
+    """C1: one 1 MiB message (2^17 blocks), one 3-key triple, encrypt then decrypt the ciphertext on one
+    stream, in and out distinct.  Kernel-only: HIP events around each launch; also the back-to-back rate
+    of whole steps (wall time over many steps), which includes the launch gaps."""
+    n = 1 << 17
+    keys = inputs.key_triple(inputs.KEY_SEED_BASE + 0)
+    sched = torch.empty(td.TDES_SCHED_BYTES, dtype=torch.uint8, device=dev)
+    td.tdes_sched_upload(td.tdes_expand_key(*keys), sched)
+    src = torch.empty(n * 8, dtype=torch.uint8, device=dev)
+    td.tdes_fill_splitmix64(src, n, inputs.DATA_SEED_BASE + 0, 0)
+    ct, pt = torch.empty_like(src), torch.empty_like(src)
+    out = {"workload": "1 MiB message (2^17 blocks), 3-key triple, encrypt then decrypt, kernel-only per launch"}
+    for name, v in (("auto", td.TDES_VARIANT_AUTO), ("table", td.TDES_VARIANT_TABLE),
+                    ("bitslice", td.TDES_VARIANT_BITSLICE)):
+        enc = time_launches(torch, lambda: td.tdes_ecb_run(sched, src, ct, n, td.TDES_ENCRYPT, v), reps)
+        dec = time_launches(torch, lambda: td.tdes_ecb_run(sched, ct, pt, n, td.TDES_DECRYPT, v), reps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            td.tdes_ecb_run(sched, src, ct, n, td.TDES_ENCRYPT, v)
+            td.tdes_ecb_run(sched, ct, pt, n, td.TDES_DECRYPT, v)
+        torch.cuda.synchronize()
+        step = (time.perf_counter() - t0) / reps
+        kernel_s = (enc + dec) / 2
+        out[name] = {"encrypt_us": round(enc * 1e6, 2), "decrypt_us": round(dec * 1e6, 2),
+                     "gbs": round(n * 8 / kernel_s / 1e9, 3),
+                     "step_us_back_to_back": round(step * 1e6, 2),
+                     "alu_frac": round(ops_per_block * n / kernel_s / 1e12 / ALU_PEAK_TOPS, 4),
+                     "roundtrip_ok": bool(torch.equal(pt, src))}
+    return out
+
+
+def bench_c3(td, torch, inputs, dev):
+    """C3: {3, 2, 1}-key triples x {2^13, 2^19, 2^25, 2^29} blocks (64 KiB .. 4 GiB) x {encrypt, decrypt},
+    the shipped automatic variant, one launch each, kernel-only (HIP events, mean of repeats)."""
+    rows = []
+    top = 1 << 29
+    src = torch.empty(top * 8, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    for keying in (3, 2, 1):
+        keys = inputs.key_triple(inputs.KEY_SEED_BASE + 3 + keying, keying)
+        sched = torch.empty(td.TDES_SCHED_BYTES, dtype=torch.uint8, device=dev)
+        td.tdes_sched_upload(td.tdes_expand_key(*keys), sched)
+        td.tdes_fill_splitmix64(src, top, inputs.DATA_SEED_BASE + 3 + 16 * keying, 0)
+        for log_n in (13, 19, 25, 29):
+            n = 1 << log_n
+            for d in (td.TDES_ENCRYPT, td.TDES_DECRYPT):
+                t = time_launches(torch, lambda: td.tdes_ecb_run(sched, src, dst, n, d, td.TDES_VARIANT_AUTO),
+                                  reps=5 if log_n >= 29 else 20)
+                rows.append({"keying": keying, "blocks": n, "direction": "decrypt" if d else "encrypt",
+                             "us": round(t * 1e6, 2), "gbs": round(n * 8 / t / 1e9, 3)})
+    return {"workload": "keying x size x direction, the automatic variant (table below 2^20 blocks, bitsliced "
+                        "from there), one launch each, kernel-only", "rows": rows}
+
+
+def bench_paper_threads(td, torch, dev):
+    """The analogue of Table I: threads per workgroup of the plain kernels under the paper's launch
+    scheme (tdes_ecb_chunked, 131072 blocks per launch) over a 512 MiB message, in place."""
+    total = 1 << 26
+    msg = torch.empty(total * 8, dtype=torch.uint8, device=dev)
+    td.tdes_fill_splitmix64(msg, total, DATA_SEED, 0)
+    sched = torch.empty(td.TDES_SCHED_BYTES, dtype=torch.uint8, device=dev)
+    from paper_1305_4376_amd import inputs
+    td.tdes_sched_upload(td.tdes_expand_key(*inputs.key_triple(KEY_SEED)), sched)
+    rows = []
+    for name, v in (("table", td.TDES_VARIANT_TABLE), ("bitslice", td.TDES_VARIANT_BITSLICE)):
+        for threads in (64, 128, 256, 512, 1024):
+            td.tdes_ecb_chunked(sched, msg, msg, 131072, 64 * 131072, variant=v, threads=threads)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            td.tdes_ecb_chunked(sched, msg, msg, 131072, total, variant=v, threads=threads)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            rows.append({"kernel": name, "threads_per_workgroup": threads, "seconds": round(dt, 5),
+                         "gbs": round(total * 8 / dt / 1e9, 3)})
+    return {"workload": "512 MiB message, in place, 512 launches of 131072 blocks (the paper's chunk), threads "
+                        "per workgroup swept for each kernel", "rows": rows}
+
+
+def cpu_baseline(sample_blocks, one_thread_blocks):
+    """The oracle on the host's cores (every core this process may use), and on one thread."""
     import oracle
     from paper_1305_4376_amd import inputs
     cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
@@ -314,9 +439,15 @@ def cpu_baseline(sample_blocks):
     t0 = time.perf_counter()
     oracle.tdes_ecb(*keys, data, decrypt=False, threads=cores)
     dt = time.perf_counter() - t0
+    one = data[: one_thread_blocks * 8]
+    t0 = time.perf_counter()
+    oracle.tdes_ecb(*keys, one, decrypt=False, threads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": round(data.size / dt / 1e9, 6), "unit": "GB/s", "cores": cores, "kind": "oracle",
             "sample": f"encrypt the first {sample_blocks} blocks ({data.size >> 20} MiB) of the benchmark message "
-                      f"with its key triple on {cores} threads: {dt:.1f} s"}
+                      f"with its key triple on {cores} threads: {dt:.1f} s",
+            "one_thread": {"value": round(one.size / dt1 / 1e9, 6), "unit": "GB/s",
+                           "sample": f"the first {one_thread_blocks} blocks on 1 thread: {dt1:.1f} s"}}
 
 
 def main():
@@ -345,16 +476,24 @@ def main():
         torch.bitwise_xor(src, 0x5A, out=ct)
         torch.cuda.synchronize()
 
+    if args.c1_only:
+        gates = circuit_gates()
+        print(json.dumps({"c1": bench_c1(td, torch, inputs, dev, 12 * gates / 8 + 120)}), flush=True)
+        return
     bytes_per_step = 2 * N_BLOCKS * 8
     # Kernel-only rate of each variant: plaintext bytes over the average launch (HIP events).
     variants = {}
     for name, v in (("table", td.TDES_VARIANT_TABLE), ("bitslice", td.TDES_VARIANT_BITSLICE)):
+        if args.plain_only:
+            break
         _, ms = time_plain(td, torch, sched, src, ct, pt, v, max(4, args.steps // 4), 2)
         variants[name] = round(N_BLOCKS * 8 / (sum(ms) / len(ms) / 1e3) / 1e9, 3)
     # CTR and CBC decryption on the same core: kernel-only rate over the same message.
     modes = {}
     iv = bytes.fromhex("0123456789abcdef")
     for name, fn in (("ctr", td.tdes_ctr_crypt), ("cbc_decrypt", td.tdes_cbc_decrypt)):
+        if args.plain_only:
+            break
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(6)]
         for i, (a, b) in enumerate([(None, None)] * 2 + ev):
             if a is not None:
@@ -394,20 +533,32 @@ def main():
     }
     del ct, pt
     torch.cuda.empty_cache()
+    if args.plain_only:
+        print(json.dumps(line), flush=True)
+        return
+    if not args.no_c1:
+        line["c1"] = bench_c1(td, torch, inputs, dev, ops_per_block)
+    if not args.no_c3:
+        del src
+        torch.cuda.empty_cache()
+        line["c3"] = bench_c3(td, torch, inputs, dev)
+        torch.cuda.empty_cache()
     if not args.no_host_path:
         line["host_path"] = bench_host_path(td, torch, sched, dev)
     if not args.no_paper_ablation:
         line["sizes"] = bench_sizes(td, torch, sched, dev)
         line["paper_scheme"] = bench_paper_scheme(td, torch, sched, dev)
+        line["paper_threads"] = bench_paper_threads(td, torch, dev)
         torch.cuda.empty_cache()
-    capacity = value * 1e9
+    capacity, tuning = value * 1e9, None
     if not args.no_batched:
-        line["batched"], capacity = bench_batched(td, torch, inputs, dev)
+        line["batched"], capacity, tuning = bench_batched(td, torch, inputs, dev, cache=args.tuning_cache)
         torch.cuda.empty_cache()
     if not args.no_serving:
-        line["serving"] = bench_serving(td, torch, inputs, dev, capacity, args.serve_seconds)
+        line["serving"] = bench_serving(td, torch, inputs, dev, capacity, args.serve_seconds, tuning,
+                                        cache=args.tuning_cache)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(args.cpu_sample_blocks)
+        line["cpu_baseline"] = cpu_baseline(args.cpu_sample_blocks, args.cpu_one_thread_blocks)
     # The paper's own figures (Table IV, seconds for a workload it sizes at 512 MB only in
     # Section III; rates derived for 512 MiB): context, not a target.
     line["paper_context"] = {"unit": "MB/s", "tesla_c2050": 26.3, "gts_250": 14.2,

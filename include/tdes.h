@@ -127,15 +127,18 @@ int tdes_ecb_run(const void *dev_sched, const void *in, void *out, uint64_t n_bl
  * The paper's host loop (Listing 1.1, Section II.B): the same operation as
  * tdes_ecb_run, issued as consecutive launches of chunk_blocks blocks each
  * (the last one shorter), all on `stream`, each with `variant`
- * (TDES_VARIANT_AUTO chooses by the chunk's size).  It exists to measure the
- * launch-granularity effect of Table II on this GPU: every launch pays the
+ * (TDES_VARIANT_AUTO chooses by the chunk's size) and workgroups of `threads`
+ * threads (0: the kernels' own, 256; else 64, 128, 256, 512 or 1024).  It
+ * exists to measure the paper's two launch parameters on this GPU: threads per
+ * workgroup (Table I) and blocks per launch (Table II).  Every launch pays the
  * launch overhead and the kernel's latency, which dominate for small chunks;
  * a single launch per message (tdes_ecb_run) or per batch (tdes_ecb_batch)
  * avoids them.
- * Errors: as tdes_ecb_run; TDES_ERR_SIZE if chunk_blocks is 0.
+ * Errors: as tdes_ecb_run; TDES_ERR_SIZE if chunk_blocks is 0; TDES_ERR_ARG
+ * for any other thread count.
  */
 int tdes_ecb_chunked(const void *dev_sched, const void *in, void *out, uint64_t n_blocks, uint64_t chunk_blocks,
-                     int direction, int variant, void *stream);
+                     int direction, int variant, uint32_t threads, void *stream);
 
 /* ---- block-parallel modes on the same round core ---- */
 
@@ -209,6 +212,8 @@ typedef struct tdes_batch_info {
     uint32_t threads;        /* threads per workgroup of the batch kernel */
     uint32_t groups_per_cu;  /* workgroups per compute unit in its grid */
     uint32_t graph_captures; /* graphs captured so far by this context */
+    uint32_t wave_remainder; /* a message's last partial tile of at least this many blocks is a wave tile */
+    uint32_t tiles_per_draw; /* tiles a wave takes per draw from the work counter */
     uint32_t pad;
 } tdes_batch_info;
 
@@ -254,11 +259,21 @@ int tdes_ecb_batch(tdes_ctx *ctx, const tdes_job *jobs, uint32_t n_jobs, const v
 int tdes_ecb_batch_replay(tdes_ctx *ctx, uint32_t flags, void *stream);
 
 /*
- * Launch shape of the batch kernel: threads per workgroup (64, 128, 192 or
- * 256) and workgroups per compute unit (1..64).  Chosen by the autotuner.
+ * Launch shape and tiling of the batch kernel, chosen by the autotuner (the
+ * paper tunes its launch by hand, Tables I and II):
+ *   threads:        threads per workgroup (64, 128, 192 or 256);
+ *   groups_per_cu:  workgroups per compute unit in the grid (1..64);
+ *   wave_remainder: a message's last partial tile of at least this many
+ *                   blocks runs as a wave tile (one key per wave), a shorter
+ *                   one as lane slots of 32 blocks packed 64 to a tile (one
+ *                   key per lane); 1..2048, 0 for the default (1800);
+ *   tiles_per_draw: tiles a wave takes per draw from the work counter after
+ *                   its first; 1..16, 0 for the default (1).
+ * Applies to the next batch (a new plan and graph capture when it changes).
  * Errors: TDES_ERR_NULL, TDES_ERR_ARG.
  */
-int tdes_ctx_set_tuning(tdes_ctx *ctx, uint32_t threads, uint32_t groups_per_cu);
+int tdes_ctx_set_tuning(tdes_ctx *ctx, uint32_t threads, uint32_t groups_per_cu, uint32_t wave_remainder,
+                        uint32_t tiles_per_draw);
 int tdes_ctx_get_info(const tdes_ctx *ctx, tdes_batch_info *info);
 
 /* ---- batched ECB without allocation ---- */
@@ -335,6 +350,8 @@ typedef struct tdes_serve_config {
     uint64_t max_step_blocks; /* blocks per step (a request larger than this runs alone) */
     uint32_t keep_outputs;    /* nonzero: outputs stay in device memory until tdes_server_release */
     uint32_t pad;
+    /* Tuning of every step's batch (tdes_ctx_set_tuning); threads == 0 keeps the library's defaults for all four. */
+    uint32_t threads, groups_per_cu, wave_remainder, tiles_per_draw;
 } tdes_serve_config;
 
 typedef struct tdes_serve_stats {

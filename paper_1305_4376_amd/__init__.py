@@ -53,7 +53,9 @@ COMPLETION_DTYPE = np.dtype([("id", "<u8"), ("user_tag", "<u8"), ("status", "<i4
 class _ServeConfig(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_uint64), ("max_inflight", ctypes.c_uint32),
                 ("max_step_jobs", ctypes.c_uint32), ("max_step_blocks", ctypes.c_uint64),
-                ("keep_outputs", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+                ("keep_outputs", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("threads", ctypes.c_uint32), ("groups_per_cu", ctypes.c_uint32),
+                ("wave_remainder", ctypes.c_uint32), ("tiles_per_draw", ctypes.c_uint32)]
 
 
 class _ServeStats(ctypes.Structure):
@@ -66,7 +68,8 @@ class _BatchInfo(ctypes.Structure):
     _fields_ = [("tiles", ctypes.c_uint64), ("wave_tiles", ctypes.c_uint64), ("lane_tiles", ctypes.c_uint64),
                 ("slots", ctypes.c_uint64), ("blocks", ctypes.c_uint64), ("padded_blocks", ctypes.c_uint64),
                 ("threads", ctypes.c_uint32), ("groups_per_cu", ctypes.c_uint32),
-                ("graph_captures", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+                ("graph_captures", ctypes.c_uint32), ("wave_remainder", ctypes.c_uint32),
+                ("tiles_per_draw", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
 
 _lib = None
 
@@ -97,7 +100,7 @@ def load_library():
         "tdes_ecb_decrypt": ([vp, vp, vp, u64, vp], i32),
         "tdes_ecb_run": ([vp, vp, vp, u64, i32, i32, vp], i32),
         "tdes_ctr_crypt": ([vp, vp, vp, vp, u64, vp], i32),
-        "tdes_ecb_chunked": ([vp, vp, vp, u64, u64, i32, i32, vp], i32),
+        "tdes_ecb_chunked": ([vp, vp, vp, u64, u64, i32, i32, u32, vp], i32),
         "tdes_cbc_decrypt": ([vp, vp, vp, vp, u64, vp], i32),
         "tdes_status_str": ([i32], ctypes.c_char_p),
         "tdes_fill_splitmix64": ([vp, u64, u64, u64, vp], i32),
@@ -106,7 +109,7 @@ def load_library():
         "tdes_ecb_batch": ([vp, vp, u32, vp, u64, vp, u32, vp], i32),
         "tdes_ecb_batch_replay": ([vp, u32, vp], i32),
         "tdes_ecb_batch_static": ([vp, u32, vp, u64, vp, u64, vp, vp], i32),
-        "tdes_ctx_set_tuning": ([vp, u32, u32], i32),
+        "tdes_ctx_set_tuning": ([vp, u32, u32, u32, u32], i32),
         "tdes_ctx_get_info": ([vp, ctypes.POINTER(_BatchInfo)], i32),
         "tdes_server_create": ([ctypes.POINTER(vp), ctypes.POINTER(_ServeConfig), vp, u64], i32),
         "tdes_server_destroy": ([vp], i32),
@@ -245,11 +248,12 @@ def _iv_buffer(iv):
 
 
 def tdes_ecb_chunked(dev_sched, src, dst, chunk_blocks: int, n_blocks=None, direction: int = TDES_ENCRYPT,
-                     variant: int = TDES_VARIANT_AUTO, stream=None) -> None:
-    """The paper's host loop: one launch per chunk of chunk_blocks blocks."""
+                     variant: int = TDES_VARIANT_AUTO, threads: int = 0, stream=None) -> None:
+    """The paper's host loop: one launch per chunk of chunk_blocks blocks, workgroups of `threads` (0: default)."""
     n = _message_args(dev_sched, src, dst, n_blocks)
     _check(load_library().tdes_ecb_chunked(_ptr(dev_sched), _ptr(src), _ptr(dst), n, int(chunk_blocks),
-                                           int(direction), int(variant), _stream(stream, src)), "tdes_ecb_chunked")
+                                           int(direction), int(variant), int(threads), _stream(stream, src)),
+           "tdes_ecb_chunked")
 
 
 def tdes_ctr_crypt(dev_sched, iv, src, dst, n_blocks=None, stream=None) -> None:
@@ -330,8 +334,10 @@ def tdes_ecb_batch_replay(ctx: int, flags: int = 0, stream=None) -> None:
     _check(load_library().tdes_ecb_batch_replay(ctx, int(flags), _stream(stream)), "tdes_ecb_batch_replay")
 
 
-def tdes_ctx_set_tuning(ctx: int, threads: int, groups_per_cu: int) -> None:
-    _check(load_library().tdes_ctx_set_tuning(ctx, int(threads), int(groups_per_cu)), "tdes_ctx_set_tuning")
+def tdes_ctx_set_tuning(ctx: int, threads: int, groups_per_cu: int, wave_remainder: int = 0,
+                        tiles_per_draw: int = 0) -> None:
+    _check(load_library().tdes_ctx_set_tuning(ctx, int(threads), int(groups_per_cu), int(wave_remainder),
+                                              int(tiles_per_draw)), "tdes_ctx_set_tuning")
 
 
 def tdes_ctx_get_info(ctx: int) -> dict:
@@ -341,11 +347,23 @@ def tdes_ctx_get_info(ctx: int) -> dict:
 
 
 def tdes_server_create(dev_sched_table, n_scheds: int, budget_bytes: int, max_inflight: int = 2,
-                       max_step_jobs: int = 4096, max_step_blocks: int = 1 << 26, keep_outputs: bool = False) -> int:
-    """Start a serving engine over a resident schedule table; returns an opaque handle."""
+                       max_step_jobs: int = 4096, max_step_blocks: int = 1 << 26, keep_outputs: bool = False,
+                       tuning=None) -> int:
+    """Start a serving engine over a resident schedule table; returns an opaque handle.  tuning: the
+    batch shape (threads, groups_per_cu, wave_remainder, tiles_per_draw) of every step, None for the
+    library's defaults, or "cached" for the shape the autotuner recorded for servers with this step
+    size on this GPU (the defaults if none)."""
     _need(dev_sched_table, int(n_scheds) * TDES_SCHED_BYTES, "schedule table")
+    if isinstance(tuning, str):
+        if tuning != "cached":
+            raise ValueError('tuning is a 4-tuple, None or "cached"')
+        from paper_1305_4376_amd import autotune
+        tuning = autotune.cached_serving(int(max_step_blocks))
+    t = tuple(int(v) for v in tuning) if tuning is not None else (0, 0, 0, 0)
+    if len(t) != 4:
+        raise ValueError("tuning is (threads, groups_per_cu, wave_remainder, tiles_per_draw)")
     cfg = _ServeConfig(int(budget_bytes), int(max_inflight), int(max_step_jobs), int(max_step_blocks),
-                       int(bool(keep_outputs)), 0)
+                       int(bool(keep_outputs)), 0, *t)
     h = ctypes.c_void_p()
     _check(load_library().tdes_server_create(ctypes.byref(h), ctypes.byref(cfg), _ptr(dev_sched_table),
                                              int(n_scheds)), "tdes_server_create")

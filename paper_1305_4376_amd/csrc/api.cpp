@@ -55,11 +55,12 @@ int check_buffers(const void *dev_sched, const void *in, const void *out, uint64
     return TDES_OK;
 }
 
-// The automatic choice, on MI355X measurements of one launch (encrypt, kernel
-// time): the bitsliced kernel costs about 40 us for anything up to 2^19 blocks
-// (one wave runs a whole 2048-block tile through all 48 rounds) and then
-// scales at about 800 GB/s; the table kernel costs 16-19 us up to 2^18 blocks
-// and scales at about 260 GB/s.  They meet near 2^20 blocks (43 vs 45 us).
+// The automatic choice, on MI355X measurements of one launch (encrypt, HIP
+// events around the launch): the bitsliced kernel costs about 36 us for
+// anything up to 2^18 blocks (one wave runs a whole 2048-block tile through all
+// 48 rounds) and then scales at about 900 GB/s; the table kernel costs 10-12 us
+// up to 2^16 blocks (14 us at 2^18) and scales at about 260 GB/s.  At 2^20
+// blocks the bitsliced kernel is already ahead (39 vs 42 us).
 int resolve_variant(int variant, uint64_t n_blocks) {
     if (variant == TDES_VARIANT_AUTO) return n_blocks < tdes::kAutoTableBelow ? TDES_VARIANT_TABLE : TDES_VARIANT_BITSLICE;
     return variant;
@@ -100,11 +101,13 @@ extern "C" int tdes_ecb_decrypt(const void *dev_sched, const void *in, void *out
 }
 
 extern "C" int tdes_ecb_chunked(const void *dev_sched, const void *in, void *out, uint64_t n_blocks,
-                                uint64_t chunk_blocks, int direction, int variant, void *stream) {
+                                uint64_t chunk_blocks, int direction, int variant, uint32_t threads, void *stream) {
     const int rc = check_buffers(dev_sched, in, out, n_blocks);
     if (rc != TDES_OK) return rc;
     if (direction != TDES_ENCRYPT && direction != TDES_DECRYPT) return TDES_ERR_ARG;
     if (variant != TDES_VARIANT_AUTO && variant != TDES_VARIANT_TABLE && variant != TDES_VARIANT_BITSLICE)
+        return TDES_ERR_ARG;
+    if (threads != 0 && threads != 64 && threads != 128 && threads != 256 && threads != 512 && threads != 1024)
         return TDES_ERR_ARG;
     if (chunk_blocks == 0) return TDES_ERR_SIZE;
     const uint32_t *ks = static_cast<const uint32_t *>(dev_sched) + direction * tdes::kDirWords;
@@ -114,8 +117,8 @@ extern "C" int tdes_ecb_chunked(const void *dev_sched, const void *in, void *out
     for (uint64_t first = 0; first < n_blocks; first += chunk_blocks) {
         const uint64_t n = n_blocks - first < chunk_blocks ? n_blocks - first : chunk_blocks;
         const hipError_t e = resolve_variant(variant, n) == TDES_VARIANT_BITSLICE
-                                 ? tdes::launch_bitslice(ks, src + 8 * first, dst + 8 * first, n, s)
-                                 : tdes::launch_table(ks, src + 8 * first, dst + 8 * first, n, s);
+                                 ? tdes::launch_bitslice(ks, src + 8 * first, dst + 8 * first, n, s, threads)
+                                 : tdes::launch_table(ks, src + 8 * first, dst + 8 * first, n, s, threads);
         if (e != hipSuccess) return TDES_ERR_HIP;
     }
     return TDES_OK;

@@ -7,9 +7,10 @@
 // batch becomes one launch of the persistent kernel in k_batch.hip.
 //
 // Planning.  Each message is cut into wave tiles of 2048 blocks (one key per
-// wave, scalar key masks).  Its remainder, if shorter than kWaveRemainder,
-// is cut into lane slots of 32 blocks instead; lane slots from all messages
-// are packed 64 to a lane tile, where each lane has its own key.  A 2048-block
+// wave, scalar key masks).  Its remainder, if shorter than the context's
+// wave_remainder (1800 unless tuned), is cut into lane slots of 32 blocks
+// instead; lane slots from all messages are packed 64 to a lane tile, where
+// each lane has its own key.  A 2048-block
 // tile then never runs mostly empty for short messages.  Lane tiles go first
 // so that the cheaper wave tiles fill the tail of the launch.
 //
@@ -32,9 +33,11 @@ namespace {
 constexpr uint32_t kWaveBlocks = 2048;
 constexpr uint32_t kLaneBlocks = 32;
 constexpr uint32_t kLanesPerTile = 64;
-// A remainder this long still takes a wave tile: a lane tile costs about 14%
-// more per block (per-lane key masks), so a wave tile wins above ~1800 blocks.
-constexpr uint32_t kWaveRemainder = 1800;
+// Default cut-over: a remainder this long still takes a wave tile.  A lane
+// tile costs about 14% more per block (per-lane key masks), so a wave tile
+// wins above ~1800 blocks; the autotuner may choose another value.
+constexpr uint32_t kDefaultWaveRemainder = 1800;
+constexpr uint32_t kMaxTilesPerDraw = 16;
 constexpr uint64_t kMaxJobBlocks = 1ull << 40;
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -57,16 +60,18 @@ struct tdes_ctx {
     const void *last_sched = nullptr;
     uint8_t *last_base = nullptr;
     uint32_t last_tiles = 0;
-    // Launch shape.
+    // Launch shape and tiling.
     uint32_t threads = 256;
     uint32_t groups_per_cu = 4;
+    uint32_t wave_remainder = kDefaultWaveRemainder;  // remainders this long take a wave tile
+    uint32_t tiles_per_draw = 1;                      // tiles a wave takes per counter draw
     // Captured graph and what it was captured for.
     hipGraphExec_t exec = nullptr;
     const void *g_sched = nullptr;
     const void *g_base = nullptr;
     const void *g_tiles = nullptr;  // every pointer the kernel node was captured with
     const void *g_slots = nullptr;
-    uint32_t g_grid = 0, g_threads = 0;
+    uint32_t g_grid = 0, g_threads = 0, g_draw = 0;
     tdes_batch_info info{};
 };
 
@@ -162,7 +167,7 @@ void plan_jobs(tdes_ctx *c, const tdes_job *jobs, uint32_t n_jobs, uint32_t *n_t
             wave.push_back({x.in_off + t * kWaveBlocks * 8, x.out_off + t * kWaveBlocks * 8, kWaveBlocks, ks_off, 0});
         if (rem == 0) continue;
         const uint64_t at = full * kWaveBlocks * 8;
-        if (rem >= kWaveRemainder) {
+        if (rem >= c->wave_remainder) {
             wave.push_back({x.in_off + at, x.out_off + at, rem, ks_off, 0});
             continue;
         }
@@ -196,13 +201,13 @@ void plan_jobs(tdes_ctx *c, const tdes_job *jobs, uint32_t n_jobs, uint32_t *n_t
 }
 
 // Upper bounds of tiles and slots for capacity, before planning.
-void count_bounds(const tdes_job *jobs, uint32_t n_jobs, size_t *tiles, size_t *slots) {
+void count_bounds(const tdes_job *jobs, uint32_t n_jobs, uint32_t wave_remainder, size_t *tiles, size_t *slots) {
     size_t wave = 0, lane = 0;
     for (uint32_t j = 0; j < n_jobs; j++) {
         const uint64_t n = jobs[j].n_blocks;
         const uint32_t rem = (uint32_t)(n % kWaveBlocks);
-        wave += n / kWaveBlocks + (rem >= kWaveRemainder ? 1 : 0);
-        if (rem && rem < kWaveRemainder) lane += (rem + kLaneBlocks - 1) / kLaneBlocks;
+        wave += n / kWaveBlocks + (rem >= wave_remainder ? 1 : 0);
+        if (rem && rem < wave_remainder) lane += (rem + kLaneBlocks - 1) / kLaneBlocks;
     }
     const size_t lane_tiles = (lane + kLanesPerTile - 1) / kLanesPerTile;
     *tiles = wave + lane_tiles;
@@ -216,11 +221,12 @@ int launch_plan(tdes_ctx *c, const void *sched, uint8_t *base, bool use_graph, h
     const tdes::Slot *slots = reinterpret_cast<const tdes::Slot *>(c->d_plan + slots_offset(c->cap_tiles));
     const uint32_t *ks = static_cast<const uint32_t *>(sched);
     if (!use_graph) {
-        if (tdes::launch_batch(ks, hdr, tiles, slots, c->d_counter, base, grid, c->threads, stream) != hipSuccess)
+        if (tdes::launch_batch(ks, hdr, tiles, slots, c->d_counter, base, grid, c->threads, c->tiles_per_draw,
+                               stream) != hipSuccess)
             return TDES_ERR_HIP;
     } else {
         if (!c->exec || c->g_sched != sched || c->g_base != base || c->g_tiles != tiles || c->g_slots != slots ||
-            c->g_grid != grid || c->g_threads != c->threads) {
+            c->g_grid != grid || c->g_threads != c->threads || c->g_draw != c->tiles_per_draw) {
             if (c->exec) {
                 (void)hipGraphExecDestroy(c->exec);
                 c->exec = nullptr;
@@ -229,7 +235,7 @@ int launch_plan(tdes_ctx *c, const void *sched, uint8_t *base, bool use_graph, h
             if (hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
                 return TDES_ERR_HIP;
             const hipError_t le = tdes::launch_batch(ks, hdr, tiles, slots, c->d_counter, base, grid, c->threads,
-                                                     c->capture_stream);
+                                                     c->tiles_per_draw, c->capture_stream);
             const hipError_t ce = hipStreamEndCapture(c->capture_stream, &graph);
             if (le != hipSuccess || ce != hipSuccess || !graph) {
                 if (graph) (void)hipGraphDestroy(graph);
@@ -247,6 +253,7 @@ int launch_plan(tdes_ctx *c, const void *sched, uint8_t *base, bool use_graph, h
             c->g_slots = slots;
             c->g_grid = grid;
             c->g_threads = c->threads;
+            c->g_draw = c->tiles_per_draw;
             c->info.graph_captures++;
         }
         if (hipGraphLaunch(c->exec, stream) != hipSuccess) return TDES_ERR_HIP;
@@ -283,6 +290,8 @@ extern "C" int tdes_ctx_create(tdes_ctx **out, int device) {
     }
     c->info.threads = c->threads;
     c->info.groups_per_cu = c->groups_per_cu;
+    c->info.wave_remainder = c->wave_remainder;
+    c->info.tiles_per_draw = c->tiles_per_draw;
     *out = c;
     return TDES_OK;
 }
@@ -303,14 +312,20 @@ extern "C" int tdes_ctx_destroy(tdes_ctx *c) {
     return TDES_OK;
 }
 
-extern "C" int tdes_ctx_set_tuning(tdes_ctx *c, uint32_t threads, uint32_t groups_per_cu) {
+extern "C" int tdes_ctx_set_tuning(tdes_ctx *c, uint32_t threads, uint32_t groups_per_cu, uint32_t wave_remainder,
+                                   uint32_t tiles_per_draw) {
     if (!c) return TDES_ERR_NULL;
     if (threads == 0 || threads > 256 || threads % 64 != 0 || groups_per_cu == 0 || groups_per_cu > 64)
         return TDES_ERR_ARG;
+    if (wave_remainder > kWaveBlocks || tiles_per_draw > kMaxTilesPerDraw) return TDES_ERR_ARG;
     c->threads = threads;
     c->groups_per_cu = groups_per_cu;
+    c->wave_remainder = wave_remainder ? wave_remainder : kDefaultWaveRemainder;
+    c->tiles_per_draw = tiles_per_draw ? tiles_per_draw : 1;
     c->info.threads = threads;
     c->info.groups_per_cu = groups_per_cu;
+    c->info.wave_remainder = c->wave_remainder;
+    c->info.tiles_per_draw = c->tiles_per_draw;
     return TDES_OK;
 }
 
@@ -349,7 +364,7 @@ extern "C" int tdes_ecb_batch(tdes_ctx *c, const tdes_job *jobs, uint32_t n_jobs
     }
 
     size_t max_tiles, max_slots;
-    count_bounds(jobs, n_jobs, &max_tiles, &max_slots);
+    count_bounds(jobs, n_jobs, c->wave_remainder, &max_tiles, &max_slots);
     if (max_tiles >= (size_t)tdes::kLaneTileBit || max_slots >= (size_t)tdes::kLaneTileBit) return TDES_ERR_SIZE;
     rc = ensure_capacity(c, max_tiles, max_slots);
     if (rc != TDES_OK) return rc;

@@ -29,6 +29,7 @@ static_assert(sizeof(Slot) == 32, "slot is 32 bytes");
 constexpr uint32_t kLaneTileBit = 0x80000000u;
 
 hipError_t launch_batch(const uint32_t *sched, const PlanHeader *hdr, const uint32_t *tiles, const Slot *slots,
-                        uint32_t *counter, uint8_t *base, uint32_t grid, uint32_t threads, hipStream_t stream);
+                        uint32_t *counter, uint8_t *base, uint32_t grid, uint32_t threads, uint32_t tiles_per_draw,
+                        hipStream_t stream);
 
 }  // namespace tdes

@@ -325,6 +325,16 @@ __device__ __forceinline__ void mode_tile(const uint32_t *__restrict__ ks, const
     }
     tdes_32_blocks<false>(a, b, ks);
     lane = opaque(lane);
+    // CBC decryption of whole tiles: the ciphertext block before the lane's first block j = 128k + 2l
+    // is the second block of lane l - 1's pair (one lane over, by a wave-wide DPP shift), and for
+    // lane 0 the last block of the previous 128 (carried in scalars; for k = 0 the block before the
+    // tile, or the IV at the message's start).
+    uint32_t carry_a = be_hi_word(iv), carry_b = be_lo_word(iv);
+    if (kMode == TileMode::kCbcDecrypt && kFull && first_block != 0) {
+        const uint2 v = *reinterpret_cast<const uint2 *>(tin - 8);
+        carry_a = __builtin_amdgcn_readfirstlane(v.x);
+        carry_b = __builtin_amdgcn_readfirstlane(v.y);
+    }
 #pragma unroll
     for (int k = 0; k < 16; k++) {
         const uint32_t j = 128 * k + 2 * lane;
@@ -340,10 +350,20 @@ __device__ __forceinline__ void mode_tile(const uint32_t *__restrict__ ks, const
                 a[2 * k] ^= v0.x; b[2 * k] ^= v0.y; a[2 * k + 1] ^= v1.x; b[2 * k + 1] ^= v1.y;
             }
         } else if constexpr (kMode == TileMode::kCbcDecrypt) {  // XOR the preceding ciphertext blocks
-            uint2 v0 = make_uint2(be_hi_word(iv), be_lo_word(iv)), v1 = make_uint2(0, 0);
-            if (first_block + j != 0 && (kFull || j < n_valid)) v0 = *reinterpret_cast<const uint2 *>(p - 8);
-            if (kFull || j + 1 < n_valid) v1 = *reinterpret_cast<const uint2 *>(p);
-            a[2 * k] ^= v0.x; b[2 * k] ^= v0.y; a[2 * k + 1] ^= v1.x; b[2 * k + 1] ^= v1.y;
+            if (kFull) {
+                const v4u v = __builtin_nontemporal_load(reinterpret_cast<const v4u *>(p));  // blocks j, j + 1
+                constexpr int kWaveShr1 = 0x138;  // DPP: lane i reads lane i - 1; lane 0 keeps the old value
+                const uint32_t pa = (uint32_t)__builtin_amdgcn_update_dpp((int)carry_a, (int)v.z, kWaveShr1, 0xF, 0xF, false);
+                const uint32_t pb = (uint32_t)__builtin_amdgcn_update_dpp((int)carry_b, (int)v.w, kWaveShr1, 0xF, 0xF, false);
+                a[2 * k] ^= pa; b[2 * k] ^= pb; a[2 * k + 1] ^= v.x; b[2 * k + 1] ^= v.y;
+                carry_a = __builtin_amdgcn_readlane(v.z, kLanes - 1);
+                carry_b = __builtin_amdgcn_readlane(v.w, kLanes - 1);
+            } else {
+                uint2 v0 = make_uint2(be_hi_word(iv), be_lo_word(iv)), v1 = make_uint2(0, 0);
+                if (first_block + j != 0 && j < n_valid) v0 = *reinterpret_cast<const uint2 *>(p - 8);
+                if (j + 1 < n_valid) v1 = *reinterpret_cast<const uint2 *>(p);
+                a[2 * k] ^= v0.x; b[2 * k] ^= v0.y; a[2 * k + 1] ^= v1.x; b[2 * k + 1] ^= v1.y;
+            }
         }
         uint8_t *q = tout + 1024 * k + 16 * lane;
         if (kFull) {

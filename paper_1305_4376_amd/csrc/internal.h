@@ -47,11 +47,13 @@ class DeviceGuard {
 };
 
 // Kernel launchers.  Arguments are already validated; n_blocks > 0.
-// `ks` points at the 96 words of one direction.
+// `ks` points at the words of one direction.  threads: workgroup size, 0 for
+// the kernel's own (256); otherwise 64, 128, 256, 512 or 1024
+// (hipErrorInvalidValue for anything else).
 hipError_t launch_table(const uint32_t *ks, const uint8_t *in, uint8_t *out, uint64_t n_blocks,
-                        hipStream_t stream);
+                        hipStream_t stream, uint32_t threads = 0);
 hipError_t launch_bitslice(const uint32_t *ks, const uint8_t *in, uint8_t *out, uint64_t n_blocks,
-                           hipStream_t stream);
+                           hipStream_t stream, uint32_t threads = 0);
 // TDES_VARIANT_AUTO: the table kernel below this many blocks, the bitsliced one from it on.
 constexpr uint64_t kAutoTableBelow = 1ull << 20;
 hipError_t launch_auto(const uint32_t *ks, const uint8_t *in, uint8_t *out, uint64_t n_blocks, hipStream_t stream);

@@ -23,15 +23,18 @@ namespace {
 
 using namespace tdes_bs;
 
-constexpr int kThreads = 256;            // 4 waves per workgroup
-constexpr int kWaves = kThreads / kLanes;
-constexpr int kMainGroupsPerCU = 4;      // 16 waves per CU: at most 128 VGPRs per lane
+constexpr int kDefaultThreads = 256;     // 4 waves per workgroup
+constexpr int kWavesPerSimd = 4;         // at most 128 VGPRs per lane
 constexpr uint64_t kMaxGrid = 1u << 20;
 
-template <TileMode kMode>
-__global__ __launch_bounds__(kThreads, kMainGroupsPerCU) void tdes_bitslice_kernel(const uint32_t *__restrict__ ks,
+// Workgroups of kThreads threads (one wave per 64); the main kernel is built for
+// four waves per SIMD whatever the workgroup size (launch_bounds' second
+// argument is the minimum number of waves per execution unit).
+template <TileMode kMode, int kThreads = kDefaultThreads>
+__global__ __launch_bounds__(kThreads, kWavesPerSimd) void tdes_bitslice_kernel(const uint32_t *__restrict__ ks,
                                                                                    const uint8_t *in, uint8_t *out,
                                                                                    uint64_t n_tiles, uint64_t iv) {
+    constexpr int kWaves = kThreads / kLanes;
     const uint32_t lane = threadIdx.x % kLanes;
     const uint64_t stride = (uint64_t)gridDim.x * kWaves;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
@@ -42,11 +45,12 @@ __global__ __launch_bounds__(kThreads, kMainGroupsPerCU) void tdes_bitslice_kern
 }
 
 // Tiles first_tile.. of the message, any of them partial; 8-byte alignment suffices.
-template <TileMode kMode>
+template <TileMode kMode, int kThreads = kDefaultThreads>
 __global__ __launch_bounds__(kThreads) void tdes_bitslice_tail_kernel(const uint32_t *__restrict__ ks,
                                                                       const uint8_t *in, uint8_t *out,
                                                                       uint64_t first_tile, uint64_t n_blocks,
                                                                       uint64_t iv) {
+    constexpr int kWaves = kThreads / kLanes;
     const uint32_t lane = threadIdx.x % kLanes;
     const uint64_t tiles = (n_blocks + kTileBlocks - 1) / kTileBlocks;
     const uint64_t stride = (uint64_t)gridDim.x * kWaves;
@@ -59,26 +63,27 @@ __global__ __launch_bounds__(kThreads) void tdes_bitslice_tail_kernel(const uint
     }
 }
 
-uint32_t grid_for(uint64_t tiles) {
-    const uint64_t g = (tiles + kWaves - 1) / kWaves;
+uint32_t grid_for(uint64_t tiles, int waves_per_group) {
+    const uint64_t g = (tiles + waves_per_group - 1) / waves_per_group;
     return (uint32_t)(g < kMaxGrid ? g : kMaxGrid);
 }
 
-template <TileMode kMode>
+template <TileMode kMode, int kThreads = kDefaultThreads>
 hipError_t launch(const uint32_t *ks, const uint8_t *in, uint8_t *out, uint64_t n_blocks, uint64_t iv,
                   hipStream_t stream) {
+    constexpr int kWaves = kThreads / kLanes;
     const bool vec16 = ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
     const uint64_t whole = vec16 ? n_blocks / kTileBlocks : 0;
     if (whole) {
-        hipLaunchKernelGGL(tdes_bitslice_kernel<kMode>, dim3(grid_for(whole)), dim3(kThreads), 0, stream, ks, in, out,
-                           whole, iv);
+        hipLaunchKernelGGL((tdes_bitslice_kernel<kMode, kThreads>), dim3(grid_for(whole, kWaves)), dim3(kThreads), 0,
+                           stream, ks, in, out, whole, iv);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if (whole * kTileBlocks < n_blocks) {
         const uint64_t rest = (n_blocks - whole * kTileBlocks + kTileBlocks - 1) / kTileBlocks;
-        hipLaunchKernelGGL(tdes_bitslice_tail_kernel<kMode>, dim3(grid_for(rest)), dim3(kThreads), 0, stream, ks, in,
-                           out, whole, n_blocks, iv);
+        hipLaunchKernelGGL((tdes_bitslice_tail_kernel<kMode, kThreads>), dim3(grid_for(rest, kWaves)), dim3(kThreads),
+                           0, stream, ks, in, out, whole, n_blocks, iv);
         return hipGetLastError();
     }
     return hipSuccess;
@@ -89,8 +94,16 @@ hipError_t launch(const uint32_t *ks, const uint8_t *in, uint8_t *out, uint64_t 
 namespace tdes {
 
 hipError_t launch_bitslice(const uint32_t *ks, const uint8_t *in, uint8_t *out, uint64_t n_blocks,
-                           hipStream_t stream) {
-    return launch<TileMode::kEcb>(ks, in, out, n_blocks, 0, stream);
+                           hipStream_t stream, uint32_t threads) {
+    switch (threads) {
+        case 0:
+        case kDefaultThreads: return launch<TileMode::kEcb>(ks, in, out, n_blocks, 0, stream);
+        case 64: return launch<TileMode::kEcb, 64>(ks, in, out, n_blocks, 0, stream);
+        case 128: return launch<TileMode::kEcb, 128>(ks, in, out, n_blocks, 0, stream);
+        case 512: return launch<TileMode::kEcb, 512>(ks, in, out, n_blocks, 0, stream);
+        case 1024: return launch<TileMode::kEcb, 1024>(ks, in, out, n_blocks, 0, stream);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_ctr(const uint32_t *ks, const uint8_t *in, uint8_t *out, uint64_t n_blocks, uint64_t iv,

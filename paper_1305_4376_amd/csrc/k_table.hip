@@ -38,7 +38,7 @@
 
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kDefaultThreads = 256;
 constexpr int kCopies = 32;
 
 constexpr uint32_t rotl32(uint32_t x, int n) { return n == 0 ? x : (x << n) | (x >> (32 - n)); }
@@ -113,84 +113,105 @@ __device__ __forceinline__ uint32_t feistel(uint32_t l5, uint32_t r5, uint32_t k
     return __builtin_amdgcn_bitop3_b32(x0, x1, x2, 0x96);
 }
 
-// Sixteen rounds; x holds L0 and y holds R0 on entry, L16 and R16 on exit.
-__device__ __forceinline__ void des_stage(uint32_t &x0, uint32_t &y0, uint32_t &x1, uint32_t &y1,
-                                          const uint32_t *__restrict__ ks, const uint8_t *lds,
-                                          uint32_t lane4) {
+// Sixteen rounds on kN blocks side by side (independent chains the scheduler
+// interleaves); x[i] holds L0 and y[i] R0 of block i on entry, L16 and R16 on exit.
+template <int kN>
+__device__ __forceinline__ void des_stage(uint32_t (&x)[kN], uint32_t (&y)[kN], const uint32_t *__restrict__ ks,
+                                          const uint8_t *lds, uint32_t lane4) {
 #pragma unroll 1
     for (int r = 0; r < 16; r += 2) {
         const uint32_t ka = ks[2 * r], kb = ks[2 * r + 1];
-        x0 = feistel(x0, y0, ka, kb, lds, lane4);
-        x1 = feistel(x1, y1, ka, kb, lds, lane4);
+#pragma unroll
+        for (int i = 0; i < kN; i++) x[i] = feistel(x[i], y[i], ka, kb, lds, lane4);
         const uint32_t ka2 = ks[2 * r + 2], kb2 = ks[2 * r + 3];
-        y0 = feistel(y0, x0, ka2, kb2, lds, lane4);
-        y1 = feistel(y1, x1, ka2, kb2, lds, lane4);
+#pragma unroll
+        for (int i = 0; i < kN; i++) y[i] = feistel(y[i], x[i], ka2, kb2, lds, lane4);
     }
 }
 
-// One lane, two blocks (w0,w1) and (w2,w3) as loaded (little-endian words).
-__device__ __forceinline__ void tdes_two_blocks(uint32_t &w0, uint32_t &w1, uint32_t &w2, uint32_t &w3,
-                                                const uint32_t *__restrict__ ks, const uint8_t *lds,
-                                                uint32_t lane4) {
-    uint32_t l0 = __builtin_bswap32(w0), r0 = __builtin_bswap32(w1);
-    uint32_t l1 = __builtin_bswap32(w2), r1 = __builtin_bswap32(w3);
-    initial_perm(l0, r0);
-    initial_perm(l1, r1);
-    l0 = rotl(l0, 5); r0 = rotl(r0, 5); l1 = rotl(l1, 5); r1 = rotl(r1, 5);
-    des_stage(l0, r0, l1, r1, ks, lds, lane4);            // stage 1: L0 = l, R0 = r
-    des_stage(r0, l0, r1, l1, ks + 32, lds, lane4);       // stage 2: halves swapped (IP^-1 then IP cancel)
-    des_stage(l0, r0, l1, r1, ks + 64, lds, lane4);       // stage 3
-    // Preoutput R16 L16 = (r, l).
-    l0 = rotl(l0, 27); r0 = rotl(r0, 27); l1 = rotl(l1, 27); r1 = rotl(r1, 27);
-    final_perm(r0, l0);
-    final_perm(r1, l1);
-    w0 = __builtin_bswap32(r0); w1 = __builtin_bswap32(l0);
-    w2 = __builtin_bswap32(r1); w3 = __builtin_bswap32(l1);
+// kN blocks of one lane, block i as the little-endian words (w[2i], w[2i+1]) as loaded.
+template <int kN>
+__device__ __forceinline__ void tdes_blocks(uint32_t (&w)[2 * kN], const uint32_t *__restrict__ ks,
+                                            const uint8_t *lds, uint32_t lane4) {
+    uint32_t l[kN], r[kN];
+#pragma unroll
+    for (int i = 0; i < kN; i++) {
+        l[i] = __builtin_bswap32(w[2 * i]);
+        r[i] = __builtin_bswap32(w[2 * i + 1]);
+        initial_perm(l[i], r[i]);
+        l[i] = rotl(l[i], 5);
+        r[i] = rotl(r[i], 5);
+    }
+    des_stage<kN>(l, r, ks, lds, lane4);       // stage 1: L0 = l, R0 = r
+    des_stage<kN>(r, l, ks + 32, lds, lane4);  // stage 2: halves swapped (IP^-1 then IP cancel)
+    des_stage<kN>(l, r, ks + 64, lds, lane4);  // stage 3
+#pragma unroll
+    for (int i = 0; i < kN; i++) {
+        // Preoutput R16 L16 = (r, l).
+        l[i] = rotl(l[i], 27);
+        r[i] = rotl(r[i], 27);
+        final_perm(r[i], l[i]);
+        w[2 * i] = __builtin_bswap32(r[i]);
+        w[2 * i + 1] = __builtin_bswap32(l[i]);
+    }
 }
 
-template <bool kVec16>
+// kPerLane blocks per lane per pass (2: one 16-byte access when kVec16; 1: an
+// 8-byte access, twice the lanes for the same message, for short messages,
+// where the 48 dependent rounds of one pass are the whole kernel time).  Each
+// lane's first load is issued before the LDS table fill so that its memory
+// latency overlaps the fill.
+template <bool kVec16, int kThreads, int kPerLane>
 __global__ __launch_bounds__(kThreads) void tdes_table_kernel(const uint32_t *__restrict__ ks, const uint8_t *in,
                                                               uint8_t *out, uint64_t n_blocks) {
     __shared__ uint4 lds4[8 * 64 * kCopies / 4];
+    const uint64_t n_units = n_blocks / kPerLane;
+    const uint64_t stride = (uint64_t)gridDim.x * kThreads;
+    uint64_t p = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    uint32_t w[2 * kPerLane];
+    auto load = [&](uint64_t q) {
+        if (kPerLane == 2 && kVec16) {
+            const uint4 v = reinterpret_cast<const uint4 *>(in)[q];
+            w[0] = v.x; w[1] = v.y; w[2 % (2 * kPerLane)] = v.z; w[3 % (2 * kPerLane)] = v.w;
+        } else {
+#pragma unroll
+            for (int i = 0; i < kPerLane; i++) {
+                const uint2 a = reinterpret_cast<const uint2 *>(in)[kPerLane * q + i];
+                w[2 * i] = a.x;
+                w[2 * i + 1] = a.y;
+            }
+        }
+    };
+    if (p < n_units) load(p);
     // 16-byte stores of four copies each, consecutive lanes on consecutive 16 bytes (no bank
     // conflicts); word w holds box 2 (w / 4096) + (w / 32) % 2, entry (w / 64) % 64.
 #pragma unroll
     for (int i = 0; i < 8 * 64 * kCopies / 4 / kThreads; i++) {
-        const int c = i * kThreads + threadIdx.x, w = 4 * c;
-        const uint32_t v = g_sp.v[2 * (w / 4096) + (w / 32) % 2][(w / 64) % 64];
+        const int c = i * kThreads + threadIdx.x, wd = 4 * c;
+        const uint32_t v = g_sp.v[2 * (wd / 4096) + (wd / 32) % 2][(wd / 64) % 64];
         lds4[c] = make_uint4(v, v, v, v);
     }
     __syncthreads();
-    const uint32_t *lds = reinterpret_cast<const uint32_t *>(lds4);
-    const uint8_t *lbase = reinterpret_cast<const uint8_t *>(lds);
+    const uint8_t *lbase = reinterpret_cast<const uint8_t *>(lds4);
     const uint32_t lane4 = (threadIdx.x % kCopies) * 4;
 
-    const uint64_t n_pairs = n_blocks / 2;
-    const uint64_t stride = (uint64_t)gridDim.x * kThreads;
-    for (uint64_t p = (uint64_t)blockIdx.x * kThreads + threadIdx.x; p < n_pairs; p += stride) {
-        uint32_t w0, w1, w2, w3;
-        if (kVec16) {
-            const uint4 v = reinterpret_cast<const uint4 *>(in)[p];
-            w0 = v.x; w1 = v.y; w2 = v.z; w3 = v.w;
+    for (; p < n_units; p += stride) {
+        tdes_blocks<kPerLane>(w, ks, lbase, lane4);
+        if (kPerLane == 2 && kVec16) {
+            reinterpret_cast<uint4 *>(out)[p] = make_uint4(w[0], w[1], w[2 % (2 * kPerLane)], w[3 % (2 * kPerLane)]);
         } else {
-            const uint2 a = reinterpret_cast<const uint2 *>(in)[2 * p];
-            const uint2 b = reinterpret_cast<const uint2 *>(in)[2 * p + 1];
-            w0 = a.x; w1 = a.y; w2 = b.x; w3 = b.y;
+#pragma unroll
+            for (int i = 0; i < kPerLane; i++)
+                reinterpret_cast<uint2 *>(out)[kPerLane * p + i] = make_uint2(w[2 * i], w[2 * i + 1]);
         }
-        tdes_two_blocks(w0, w1, w2, w3, ks, lbase, lane4);
-        if (kVec16) {
-            reinterpret_cast<uint4 *>(out)[p] = make_uint4(w0, w1, w2, w3);
-        } else {
-            reinterpret_cast<uint2 *>(out)[2 * p] = make_uint2(w0, w1);
-            reinterpret_cast<uint2 *>(out)[2 * p + 1] = make_uint2(w2, w3);
-        }
+        if (p + stride < n_units) load(p + stride);
     }
-    // An odd final block: the first lane of the grid takes it alone.
-    if ((n_blocks & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    // An odd final block (two blocks per lane): the first lane of the grid takes it alone.
+    if (kPerLane == 2 && (n_blocks & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
         const uint2 a = reinterpret_cast<const uint2 *>(in)[n_blocks - 1];
-        uint32_t w0 = a.x, w1 = a.y, w2 = 0, w3 = 0;
-        tdes_two_blocks(w0, w1, w2, w3, ks, lbase, lane4);
-        reinterpret_cast<uint2 *>(out)[n_blocks - 1] = make_uint2(w0, w1);
+        uint32_t v[2] = {a.x, a.y};
+        tdes_blocks<1>(v, ks, lbase, lane4);
+        reinterpret_cast<uint2 *>(out)[n_blocks - 1] = make_uint2(v[0], v[1]);
     }
 }
 
@@ -199,22 +220,36 @@ __global__ __launch_bounds__(kThreads) void tdes_table_kernel(const uint32_t *__
 namespace tdes {
 
 hipError_t launch_table(const uint32_t *ks, const uint8_t *in, uint8_t *out, uint64_t n_blocks,
-                        hipStream_t stream) {
+                        hipStream_t stream, uint32_t threads) {
     DeviceInfo info;
     if (device_info(&info) != TDES_OK) return hipErrorInvalidDevice;
-    const uint64_t n_pairs = n_blocks / 2;
-    uint64_t grid = (n_pairs + kThreads - 1) / kThreads;
-    const uint64_t resident = (uint64_t)info.cu_count * 2;  // 64 KiB of LDS per workgroup
+    if (threads == 0) threads = kDefaultThreads;
+    // 64 KiB of LDS per workgroup: two per CU (the compiler fits the registers of every size to that)
+    const uint64_t resident = (uint64_t)info.cu_count * 2;
+    // One block per lane while one pass of the resident grid covers the message, else two.
+    const int per_lane = n_blocks <= resident * threads ? 1 : 2;
+    const uint64_t units = n_blocks / per_lane;
+    uint64_t grid = (units + threads - 1) / threads;
     if (grid > resident) grid = resident;
     if (grid == 0) grid = 1;
     const bool vec16 = ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
-    if (vec16)
-        hipLaunchKernelGGL(tdes_table_kernel<true>, dim3((unsigned)grid), dim3(kThreads), 0, stream, ks, in, out,
-                           n_blocks);
-    else
-        hipLaunchKernelGGL(tdes_table_kernel<false>, dim3((unsigned)grid), dim3(kThreads), 0, stream, ks, in, out,
-                           n_blocks);
-    return hipGetLastError();
+    auto go = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3(threads), 0, stream, ks, in, out, n_blocks);
+        return hipGetLastError();
+    };
+#define TDES_TABLE_CASE(T)                                                              \
+    case T:                                                                             \
+        if (per_lane == 1) return go(tdes_table_kernel<false, T, 1>);                   \
+        return vec16 ? go(tdes_table_kernel<true, T, 2>) : go(tdes_table_kernel<false, T, 2>);
+    switch (threads) {
+        TDES_TABLE_CASE(64)
+        TDES_TABLE_CASE(128)
+        TDES_TABLE_CASE(256)
+        TDES_TABLE_CASE(512)
+        TDES_TABLE_CASE(1024)
+        default: return hipErrorInvalidValue;
+    }
+#undef TDES_TABLE_CASE
 }
 
 }  // namespace tdes

@@ -389,6 +389,10 @@ extern "C" int tdes_server_create(tdes_server **out, const tdes_serve_config *cf
     if (cfg->budget_bytes < 2 * kAlign || cfg->max_inflight == 0 || cfg->max_inflight > kMaxInflight ||
         cfg->max_step_jobs == 0 || cfg->max_step_blocks == 0)
         return TDES_ERR_ARG;
+    // The batch tuning (tdes_ctx_set_tuning's ranges), checked before anything is allocated.
+    if (cfg->threads && (cfg->threads > 256 || cfg->threads % 64 || cfg->groups_per_cu == 0 ||
+                         cfg->groups_per_cu > 64 || cfg->wave_remainder > 2048 || cfg->tiles_per_draw > 16))
+        return TDES_ERR_ARG;
     tdes_server *s = new (std::nothrow) tdes_server;
     if (!s) return TDES_ERR_NOMEM;
     s->cfg = *cfg;
@@ -408,6 +412,8 @@ extern "C" int tdes_server_create(tdes_server **out, const tdes_serve_config *cf
     s->steps.resize(cfg->max_inflight);
     for (Step &st : s->steps) {
         if (tdes_ctx_create(&st.ctx, s->device) != TDES_OK ||
+            (cfg->threads && tdes_ctx_set_tuning(st.ctx, cfg->threads, cfg->groups_per_cu, cfg->wave_remainder,
+                                                 cfg->tiles_per_draw) != TDES_OK) ||
             hipStreamCreateWithFlags(&st.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&st.done, hipEventDisableTiming) != hipSuccess ||
             hipEventCreateWithFlags(&st.fill_staged, hipEventDisableTiming) != hipSuccess) {

@@ -179,23 +179,25 @@ def test_batch_rejects_bad_jobs():
         ok = jobs.copy(); ok["out_off"] = ok["in_off"]                  # in place is fine
         td.tdes_ecb_batch(ctx, ok, table, 2, buf, 0)
         torch.cuda.synchronize()
-        with pytest.raises(td.TdesError) as e:
-            td.tdes_ctx_set_tuning(ctx, 96, 2)
-        assert e.value.code == -7
+        for bad_shape in ((96, 2), (64, 1, 2049), (64, 1, 0, 17)):
+            with pytest.raises(td.TdesError) as e:
+                td.tdes_ctx_set_tuning(ctx, *bad_shape)
+            assert e.value.code == -7
     finally:
         td.tdes_ctx_destroy(ctx)
 
 
-def test_replays_with_more_tiles_than_waves():
-    """A small grid (one 64-thread workgroup per CU) takes most tiles from the work counter, so each
-    replay relies on the previous launch having left the counter at zero."""
+@pytest.mark.parametrize("per_draw", [1, 3])
+def test_replays_with_more_tiles_than_waves(per_draw):
+    """A small grid (one 64-thread workgroup per CU) takes most tiles from the work counter, one or
+    three per draw, so each replay relies on the previous launch having left the counter at zero."""
     keys, table = _table(16, 0xB21)
     lengths = inputs.log_uniform_lengths(0xB22, 400, 40000)
     jobs, buf, total = _layout(lengths, 0xB23)
     jobs["sched_idx"] = np.arange(len(lengths)) % 16
     ctx = td.tdes_ctx_create()
     try:
-        td.tdes_ctx_set_tuning(ctx, 64, 1)
+        td.tdes_ctx_set_tuning(ctx, 64, 1, 0, per_draw)
         td.tdes_ecb_batch(ctx, jobs, table, 16, buf, td.TDES_BATCH_NO_GRAPH)
         torch.cuda.synchronize()
         info = td.tdes_ctx_get_info(ctx)
@@ -217,16 +219,27 @@ def test_replays_with_more_tiles_than_waves():
         td.tdes_ctx_destroy(ctx)
 
 
-@pytest.mark.parametrize("shape", [(64, 1), (128, 2), (256, 1), (256, 6), (192, 3)])
+@pytest.mark.parametrize("shape", [(64, 1, 0, 0), (128, 2, 1, 3), (256, 1, 2048, 2), (256, 6, 512, 16),
+                                   (192, 3, 1800, 1)])
 def test_batch_tuning_shapes(shape):
+    """Launch shapes and tilings (threads, workgroups per CU, wave/lane cut-over, tiles per draw):
+    every message still matches the oracle."""
     keys, table = _table(5, 0xB31)
     lengths = inputs.log_uniform_lengths(0xB32, 200, 10000)
-    jobs, buf, _ = _layout(lengths, 0xB33)
+    jobs, buf, total = _layout(lengths, 0xB33)
     jobs["sched_idx"] = np.arange(len(lengths)) % 5
     ctx = td.tdes_ctx_create()
     try:
         td.tdes_ctx_set_tuning(ctx, *shape)
         td.tdes_ecb_batch(ctx, jobs, table, 5, buf, 0)
+        torch.cuda.synchronize()
+        info = td.tdes_ctx_get_info(ctx)
+        assert (info["threads"], info["groups_per_cu"]) == shape[:2]
+        assert info["wave_remainder"] == (shape[2] or 1800) and info["tiles_per_draw"] == (shape[3] or 1)
+        _check_jobs(jobs, keys, buf, 0xB33, sample_per_job=48)
+        buf[total:2 * total].zero_()
+        torch.cuda.synchronize()
+        td.tdes_ecb_batch_replay(ctx, 0)  # graph replay under the same tuning
         torch.cuda.synchronize()
         _check_jobs(jobs, keys, buf, 0xB33, sample_per_job=48)
     finally:

@@ -216,9 +216,9 @@ def test_chunked_launches_match_oracle(variant):
     against the oracle: chunk sizes from one block to past the message, a short last chunk, and the
     paper's 131072 blocks per launch on a message that also spans a 2^20-block chunk (where the
     automatic variant switches to the bitsliced kernel)."""
-    cases = [(3 * 2048 * 5 + 777, (1, 100, 2048, 4096 + 8, 3 * 2048 * 5 + 777, 2 * (3 * 2048 * 5 + 777))),
-             ((1 << 20) + 3 * 2048 + 777, (131072, 1 << 20))]
-    for ci, (n, chunks) in enumerate(cases):
+    cases = [(3 * 2048 * 5 + 777, (1, 100, 2048, 4096 + 8, 3 * 2048 * 5 + 777, 2 * (3 * 2048 * 5 + 777)), (0,)),
+             ((1 << 20) + 3 * 2048 + 777, (131072, 1 << 20), (0, 64, 128, 256, 512, 1024))]
+    for ci, (n, chunks, thread_counts) in enumerate(cases):
         seed = inputs.DATA_SEED_BASE + 90 + ci
         keys = inputs.key_triple(inputs.KEY_SEED_BASE + 90 + ci)
         sched = _gpu.device_sched(*keys)
@@ -226,14 +226,20 @@ def test_chunked_launches_match_oracle(variant):
         src = _gpu.to_device(host)
         want = {d: _gpu.oracle_on_blocks(keys, host, decrypt=d == td.TDES_DECRYPT) for d in DIRS}
         for chunk in chunks:
-            for d in DIRS:
-                print(f"[parity] chunked variant={variant} n={n} chunk={chunk} dir={d}", flush=True)
-                out = torch.empty_like(src)
-                td.tdes_ecb_chunked(sched, src, out, chunk, n, direction=d, variant=variant)
-                torch.cuda.synchronize()
-                got = out.cpu().numpy()
-                assert np.array_equal(got, want[d]), \
-                    f"chunk {chunk}: first mismatch at block {np.argmax((got != want[d]).reshape(-1, 8).any(1))}"
+            for threads in thread_counts:
+                for d in DIRS:
+                    print(f"[parity] chunked variant={variant} n={n} chunk={chunk} threads={threads} dir={d}",
+                          flush=True)
+                    out = torch.empty_like(src)
+                    td.tdes_ecb_chunked(sched, src, out, chunk, n, direction=d, variant=variant, threads=threads)
+                    torch.cuda.synchronize()
+                    got = out.cpu().numpy()
+                    assert np.array_equal(got, want[d]), \
+                        f"chunk {chunk}, {threads} threads: first mismatch at block " \
+                        f"{np.argmax((got != want[d]).reshape(-1, 8).any(1))}"
         with pytest.raises(td.TdesError) as e:
             td.tdes_ecb_chunked(sched, src, src, 0, n, variant=variant)
         assert e.value.code == -4
+        with pytest.raises(td.TdesError) as e:
+            td.tdes_ecb_chunked(sched, src, src, 131072, n, variant=variant, threads=192)
+        assert e.value.code == -7

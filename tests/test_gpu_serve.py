@@ -117,6 +117,34 @@ def test_alone_equals_in_the_mix(table):
         _check_oracle(keys, reqs[i], mixed[i])
 
 
+def test_tuned_steps_every_block(table):
+    """Steps under a non-default batch shape (128 threads, 8 groups per CU, every remainder as a
+    wave tile below 1024 blocks, two tiles per draw): every block of every request against the oracle."""
+    keys, dev_table = table
+    reqs = _requests(160, 0x5E1F, max_blocks=1 << 16)
+    server = td.tdes_server_create(dev_table, N_KEYS, 1 << 30, max_inflight=3, max_step_jobs=48,
+                                   keep_outputs=True, tuning=(128, 8, 1024, 2))
+    try:
+        arrival = np.sort(np.random.default_rng(16).uniform(0, 0.01, reqs.size))
+        print(f"[serve] tuned steps: {reqs.size} requests", flush=True)
+        done = td.tdes_server_run_trace(server, reqs, arrival)
+        assert (done["status"] == 0).all()
+        assert td.tdes_server_stats(server)["steps"] > 1
+        mixed = _outputs_by_tag(server, done, reqs)
+    finally:
+        td.tdes_server_destroy(server)
+    for i in range(reqs.size):
+        _check_oracle(keys, reqs[i], mixed[i])
+
+
+def test_server_rejects_bad_tuning(table):
+    _, dev_table = table
+    for kw in ({"tuning": (96, 4, 0, 0)}, {"tuning": (256, 4, 4096, 0)}, {"tuning": (256, 4, 0, 17)}):
+        with pytest.raises(td.TdesError) as e:
+            td.tdes_server_create(dev_table, N_KEYS, 1 << 20, **kw)
+        assert e.value.code == -7, kw
+
+
 def test_budget_admission_and_cancel(table):
     keys, dev_table = table
     budget = 64 << 20

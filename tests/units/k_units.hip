@@ -106,9 +106,80 @@ __global__ void folded_stage_kernel(const uint32_t *blocks, const uint32_t *dir_
     for (int k = 0; k < 32; k++) { out[k] = l[k]; out[32 + k] = r[k]; }
 }
 
+// ---- VALU issue-rate probe ----
+//
+// Each wave runs `iters` times a block of 128 VALU instructions of one kind on
+// fixed registers (destinations v8..v23, sources v24..v55, never written, so
+// no instruction waits on another), between two reads of the shader clock
+// counter (s_memtime) and the 100 MHz real-time counter (s_memrealtime).
+// A VGPR's bank is its index mod 4; row i's three sources sit in banks 0, 1
+// and 2, and its fourth operand is a second bank-0 register.
+#define PROBE_ROWS(M) \
+    M(8, 24, 37, 46, 28) M(9, 28, 41, 50, 32) M(10, 32, 45, 54, 36) M(11, 36, 49, 26, 40) \
+    M(12, 40, 53, 30, 44) M(13, 44, 25, 34, 48) M(14, 48, 29, 38, 52) M(15, 52, 33, 42, 24) \
+    M(16, 24, 37, 46, 28) M(17, 28, 41, 50, 32) M(18, 32, 45, 54, 36) M(19, 36, 49, 26, 40) \
+    M(20, 40, 53, 30, 44) M(21, 44, 25, 34, 48) M(22, 48, 29, 38, 52) M(23, 52, 33, 42, 24)
+#define P_XOR(D, A, B, C, A2) "v_xor_b32 v" #D ", v" #A ", v" #B "\n"
+#define P_ADD(D, A, B, C, A2) "v_add_u32 v" #D ", v" #A ", v" #B "\n"
+#define P_LSHR(D, A, B, C, A2) "v_lshrrev_b32 v" #D ", 4, v" #A "\n"
+#define P_LSHL(D, A, B, C, A2) "v_lshlrev_b32 v" #D ", 4, v" #A "\n"
+#define P_BITOP3(D, A, B, C, A2) "v_bitop3_b32 v" #D ", v" #A ", v" #B ", v" #C " bitop3:0x96\n"
+#define P_BITOP3_SAME(D, A, B, C, A2) "v_bitop3_b32 v" #D ", v" #A ", v" #A2 ", v" #C " bitop3:0x96\n"
+#define P_PERM(D, A, B, C, A2) "v_perm_b32 v" #D ", v" #A ", v" #B ", v" #C "\n"
+#define PROBE_CLOBBERS                                                                                       \
+    "v8", "v9", "v10", "v11", "v12", "v13", "v14", "v15", "v16", "v17", "v18", "v19", "v20", "v21", "v22", "v23", \
+        "v24", "v25", "v26", "v27", "v28", "v29", "v30", "v31", "v32", "v33", "v34", "v35", "v36", "v37", "v38",   \
+        "v39", "v40", "v41", "v42", "v43", "v44", "v45", "v46", "v47", "v48", "v49", "v50", "v51", "v52", "v53",   \
+        "v54", "v55"
+#define PROBE_BLOCK(M) PROBE_ROWS(M) PROBE_ROWS(M) PROBE_ROWS(M) PROBE_ROWS(M) \
+    PROBE_ROWS(M) PROBE_ROWS(M) PROBE_ROWS(M) PROBE_ROWS(M)
+#define PROBE_CASE(K, M)                                                                   \
+    case K:                                                                                \
+        for (int i = 0; i < iters; i++) asm volatile(PROBE_BLOCK(M)::: PROBE_CLOBBERS);    \
+        break;
+
+// clk[6 w + 0..5] for wave w: shader-clock count before and after, real-time count before and
+// after, the wave's HW_ID register (SIMD, CU, shader array and engine fields) and its XCC_ID.
+__global__ __launch_bounds__(256) void issue_probe_kernel(int op, int iters, uint64_t *clk) {
+    const uint64_t c0 = __builtin_readcyclecounter();
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    switch (op) {
+        PROBE_CASE(0, P_XOR)
+        PROBE_CASE(1, P_ADD)
+        PROBE_CASE(2, P_LSHR)
+        PROBE_CASE(3, P_LSHL)
+        PROBE_CASE(4, P_BITOP3)
+        PROBE_CASE(5, P_BITOP3_SAME)
+        PROBE_CASE(6, P_PERM)
+        default:
+            break;
+    }
+    const uint64_t c1 = __builtin_readcyclecounter();
+    const uint64_t t1 = __builtin_amdgcn_s_memrealtime();
+    uint32_t hw_id, xcc_id;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_HW_ID)" : "=s"(hw_id));
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc_id));
+    if (threadIdx.x % 64 == 0) {
+        const uint32_t w = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+        clk[6 * w + 0] = c0;
+        clk[6 * w + 1] = c1;
+        clk[6 * w + 2] = t0;
+        clk[6 * w + 3] = t1;
+        clk[6 * w + 4] = hw_id;
+        clk[6 * w + 5] = xcc_id;
+    }
+}
+
 int status() { return hipGetLastError() == hipSuccess && hipDeviceSynchronize() == hipSuccess ? 0 : -1; }
 
 }  // namespace
+
+// groups workgroups of 256 threads; dev_clk holds 6 * 4 * groups words.
+extern "C" int units_issue_probe(int op, int groups, int iters, uint64_t *dev_clk) {
+    if (op < 0 || op > 6 || groups < 1 || iters < 1) return -1;
+    hipLaunchKernelGGL(issue_probe_kernel, dim3(groups), dim3(256), 0, 0, op, iters, dev_clk);
+    return status();
+}
 
 extern "C" int units_sbox(uint32_t *dev_out) {
     hipLaunchKernelGGL(sbox_kernel, dim3(1), dim3(1), 0, 0, dev_out);
