@@ -181,16 +181,54 @@ __device__ __forceinline__ void fold_fix(uint32_t (&h)[32], uint32_t w_in) {
     for (int q = 0; q < 32; q++) h[q] ^= key_mask(w, q);
 }
 
+// The same two rounds as generated gfx950 assembly (rounds_asm.inc, written
+// by gen/gen_rounds.py from the stored circuits and the standard's E and P,
+// and checked there against this file's definition by simulation): x ^= f(y)
+// with (ow0, cw0), then y ^= f(x) with (ow1, cw1).  The generator assigns the
+// registers itself so that an instruction's vector operands sit in different
+// register banks (bank = register number mod 4; two operands in one bank
+// halve the issue rate, and the compiler's own assignment of this code has
+// that in nearly half its instructions).  The 64 planes live in two fixed
+// register sets; kSwapped: x in the second set and y in the first, which is
+// how the halves lie in the middle DES stage of EDE.
+#include "rounds_asm.inc"
+
+template <bool kSwapped>
+__device__ __forceinline__ void feistel_pair_asm(uint32_t (&x)[32], uint32_t (&y)[32], uint32_t ow0, uint32_t cw0,
+                                                 uint32_t ow1, uint32_t cw1) {
+    if constexpr (!kSwapped)
+        asm volatile(TDES_ROUNDS_ASM_A
+                     : TDES_ROUNDS_OPERANDS_A(x, y)
+                     : [ow0] "s"(ow0), [cw0] "s"(cw0), [ow1] "s"(ow1), [cw1] "s"(cw1)
+                     : TDES_ROUNDS_CLOBBERS);
+    else
+        asm volatile(TDES_ROUNDS_ASM_B
+                     : TDES_ROUNDS_OPERANDS_B(x, y)
+                     : [ow0] "s"(ow0), [cw0] "s"(cw0), [ow1] "s"(ow1), [cw1] "s"(cw1)
+                     : TDES_ROUNDS_CLOBBERS);
+}
+
 // The 16 rounds of stage `stage` (0..2) with folded masks: x holds L0 and y
 // holds R0 on entry, L16 and R16 on exit; y enters folded with the stage's
-// first key and x leaves folded with its last.  fold: the direction's folded words.
+// first key and x leaves folded with its last.  fold: the direction's folded
+// words.  kSwapped: see feistel_pair_asm.
+template <bool kSwapped = false>
 __device__ __forceinline__ void des_rounds_folded(uint32_t (&x)[32], uint32_t (&y)[32],
                                                   const uint32_t *__restrict__ fold, int stage) {
     const uint32_t *ow = fold + kFoldOut + 16 * stage, *cw = fold + kFoldCorr + 16 * stage;
+    // The next pair's words are loaded before this pair's rounds run, so their
+    // scalar loads complete behind the rounds instead of stalling the wave.
+    uint32_t o0 = ow[0], c0 = cw[0], o1 = ow[1], c1 = cw[1];
 #pragma unroll 1
     for (int r = 0; r < 16; r += 2) {
-        feistel_folded(x, y, ow[r], cw[r]);
-        feistel_folded(y, x, ow[r + 1], cw[r + 1]);
+        const uint32_t ko0 = key_word<false>(o0), kc0 = key_word<false>(c0);
+        const uint32_t ko1 = key_word<false>(o1), kc1 = key_word<false>(c1);
+        const int n = r + 2 < 16 ? r + 2 : r;  // (the last pair reloads its own words)
+        o0 = ow[n];
+        c0 = cw[n];
+        o1 = ow[n + 1];
+        c1 = cw[n + 1];
+        feistel_pair_asm<kSwapped>(x, y, ko0, kc0, ko1, kc1);
     }
 }
 
@@ -243,7 +281,7 @@ __device__ __forceinline__ void tdes_32_blocks(uint32_t (&a)[32], uint32_t (&b)[
         fold_fix(r, fold[kFoldPre + 0]);
         des_rounds_folded(l, r, fold, 0);
         fold_fix(l, fold[kFoldMid + 0]);
-        des_rounds_folded(r, l, fold, 1);
+        des_rounds_folded<true>(r, l, fold, 1);
         fold_fix(r, fold[kFoldMid + 1]);
         des_rounds_folded(l, r, fold, 2);
         fold_fix(l, fold[kFoldPost + 2]);
