@@ -408,7 +408,8 @@ def emit_inc(pairs, seed) -> str:
             out.append(f'    "{l}\\n" \\')
         out.append("")
     out.append("#define TDES_ROUNDS_CLOBBERS \\")
-    clob = [f'"v{r}"' for r in used_v] + [f'"s{r}"' for r in SGPR_POOL]
+    # s_bfe_i32 also writes SCC
+    clob = [f'"v{r}"' for r in used_v] + [f'"s{r}"' for r in SGPR_POOL] + ['"scc"']
     for i in range(0, len(clob), 12):
         out.append("    " + ", ".join(clob[i:i + 12]) + (", \\" if i + 12 < len(clob) else ""))
     out.append("")
