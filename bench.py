@@ -38,7 +38,7 @@ KEY_SEED = 0x4B455900 + 1
 ALU_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 PKG = os.path.join(ROOT, "paper_1305_4376_amd")
-KERNEL_SOURCES = ["csrc/bitslice_core.h", "csrc/k_bitslice.hip", "csrc/sbox_circuits.inc"]
+KERNEL_SOURCES = ["csrc/bitslice_core.h", "csrc/k_bitslice.hip", "csrc/sbox_circuits.inc", "csrc/rounds_asm.inc"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tdes_bitslice_kernel_1GiB_traffic.md")
 
 

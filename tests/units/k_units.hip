@@ -126,6 +126,17 @@ __global__ void folded_stage_kernel(const uint32_t *blocks, const uint32_t *dir_
 #define P_BITOP3(D, A, B, C, A2) "v_bitop3_b32 v" #D ", v" #A ", v" #B ", v" #C " bitop3:0x96\n"
 #define P_BITOP3_SAME(D, A, B, C, A2) "v_bitop3_b32 v" #D ", v" #A ", v" #A2 ", v" #C " bitop3:0x96\n"
 #define P_PERM(D, A, B, C, A2) "v_perm_b32 v" #D ", v" #A ", v" #B ", v" #C "\n"
+// Dependent chains: each instruction reads the result of the one d instructions before it (d = 1, 2, 4),
+// sources in three banks.
+#define PROBE_CHAIN1 "v_bitop3_b32 v8, v8, v25, v38 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v29, v42 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v33, v46 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v37, v50 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v41, v54 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v45, v26 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v49, v30 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v53, v34 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v25, v38 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v29, v42 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v33, v46 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v37, v50 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v41, v54 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v45, v26 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v49, v30 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v53, v34 bitop3:0x96\n"
+#define PROBE_CHAIN2 "v_bitop3_b32 v8, v8, v25, v38 bitop3:0x96\n" "v_bitop3_b32 v12, v12, v29, v42 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v33, v46 bitop3:0x96\n" "v_bitop3_b32 v12, v12, v37, v50 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v41, v54 bitop3:0x96\n" "v_bitop3_b32 v12, v12, v45, v26 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v49, v30 bitop3:0x96\n" "v_bitop3_b32 v12, v12, v53, v34 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v25, v38 bitop3:0x96\n" "v_bitop3_b32 v12, v12, v29, v42 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v33, v46 bitop3:0x96\n" "v_bitop3_b32 v12, v12, v37, v50 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v41, v54 bitop3:0x96\n" "v_bitop3_b32 v12, v12, v45, v26 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v49, v30 bitop3:0x96\n" "v_bitop3_b32 v12, v12, v53, v34 bitop3:0x96\n"
+#define PROBE_CHAIN4 "v_bitop3_b32 v8, v8, v25, v38 bitop3:0x96\n" "v_bitop3_b32 v12, v12, v29, v42 bitop3:0x96\n" "v_bitop3_b32 v16, v16, v33, v46 bitop3:0x96\n" "v_bitop3_b32 v20, v20, v37, v50 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v41, v54 bitop3:0x96\n" "v_bitop3_b32 v12, v12, v45, v26 bitop3:0x96\n" "v_bitop3_b32 v16, v16, v49, v30 bitop3:0x96\n" "v_bitop3_b32 v20, v20, v53, v34 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v25, v38 bitop3:0x96\n" "v_bitop3_b32 v12, v12, v29, v42 bitop3:0x96\n" "v_bitop3_b32 v16, v16, v33, v46 bitop3:0x96\n" "v_bitop3_b32 v20, v20, v37, v50 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v41, v54 bitop3:0x96\n" "v_bitop3_b32 v12, v12, v45, v26 bitop3:0x96\n" "v_bitop3_b32 v16, v16, v49, v30 bitop3:0x96\n" "v_bitop3_b32 v20, v20, v53, v34 bitop3:0x96\n"
+#define PROBE_CHAIN3 "v_bitop3_b32 v8, v8, v25, v38 bitop3:0x96\n" "v_bitop3_b32 v12, v12, v29, v42 bitop3:0x96\n" "v_bitop3_b32 v16, v16, v33, v46 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v37, v50 bitop3:0x96\n" "v_bitop3_b32 v12, v12, v41, v54 bitop3:0x96\n" "v_bitop3_b32 v16, v16, v45, v26 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v49, v30 bitop3:0x96\n" "v_bitop3_b32 v12, v12, v53, v34 bitop3:0x96\n" "v_bitop3_b32 v16, v16, v25, v38 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v29, v42 bitop3:0x96\n" "v_bitop3_b32 v12, v12, v33, v46 bitop3:0x96\n" "v_bitop3_b32 v16, v16, v37, v50 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v41, v54 bitop3:0x96\n" "v_bitop3_b32 v12, v12, v45, v26 bitop3:0x96\n" "v_bitop3_b32 v16, v16, v49, v30 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v53, v34 bitop3:0x96\n"
+#define PROBE_CHAIN8 "v_bitop3_b32 v8, v8, v25, v38 bitop3:0x96\n" "v_bitop3_b32 v12, v12, v29, v42 bitop3:0x96\n" "v_bitop3_b32 v16, v16, v33, v46 bitop3:0x96\n" "v_bitop3_b32 v20, v20, v37, v50 bitop3:0x96\n" "v_bitop3_b32 v24, v24, v41, v54 bitop3:0x96\n" "v_bitop3_b32 v28, v28, v45, v26 bitop3:0x96\n" "v_bitop3_b32 v32, v32, v49, v30 bitop3:0x96\n" "v_bitop3_b32 v36, v36, v53, v34 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v25, v38 bitop3:0x96\n" "v_bitop3_b32 v12, v12, v29, v42 bitop3:0x96\n" "v_bitop3_b32 v16, v16, v33, v46 bitop3:0x96\n" "v_bitop3_b32 v20, v20, v37, v50 bitop3:0x96\n" "v_bitop3_b32 v24, v24, v41, v54 bitop3:0x96\n" "v_bitop3_b32 v28, v28, v45, v26 bitop3:0x96\n" "v_bitop3_b32 v32, v32, v49, v30 bitop3:0x96\n" "v_bitop3_b32 v36, v36, v53, v34 bitop3:0x96\n"
+#define PROBE_CHAIN4R "v_bitop3_b32 v8, v8, v25, v38 bitop3:0x96\n" "v_bitop3_b32 v9, v9, v30, v43 bitop3:0x96\n" "v_bitop3_b32 v10, v10, v35, v44 bitop3:0x96\n" "v_bitop3_b32 v11, v11, v36, v49 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v41, v54 bitop3:0x96\n" "v_bitop3_b32 v9, v9, v46, v27 bitop3:0x96\n" "v_bitop3_b32 v10, v10, v51, v28 bitop3:0x96\n" "v_bitop3_b32 v11, v11, v52, v33 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v25, v38 bitop3:0x96\n" "v_bitop3_b32 v9, v9, v30, v43 bitop3:0x96\n" "v_bitop3_b32 v10, v10, v35, v44 bitop3:0x96\n" "v_bitop3_b32 v11, v11, v36, v49 bitop3:0x96\n" "v_bitop3_b32 v8, v8, v41, v54 bitop3:0x96\n" "v_bitop3_b32 v9, v9, v46, v27 bitop3:0x96\n" "v_bitop3_b32 v10, v10, v51, v28 bitop3:0x96\n" "v_bitop3_b32 v11, v11, v52, v33 bitop3:0x96\n"
+// Independent v_bitop3_b32 with sources in banks 0, 1, 2 and the result in bank 3 or in bank 0.
+#define PROBE_DST3 "v_bitop3_b32 v11, v24, v37, v46 bitop3:0x96\n" "v_bitop3_b32 v15, v28, v41, v50 bitop3:0x96\n" "v_bitop3_b32 v19, v32, v45, v54 bitop3:0x96\n" "v_bitop3_b32 v23, v36, v49, v26 bitop3:0x96\n" "v_bitop3_b32 v11, v40, v53, v30 bitop3:0x96\n" "v_bitop3_b32 v15, v44, v25, v34 bitop3:0x96\n" "v_bitop3_b32 v19, v48, v29, v38 bitop3:0x96\n" "v_bitop3_b32 v23, v52, v33, v42 bitop3:0x96\n" "v_bitop3_b32 v11, v24, v37, v46 bitop3:0x96\n" "v_bitop3_b32 v15, v28, v41, v50 bitop3:0x96\n" "v_bitop3_b32 v19, v32, v45, v54 bitop3:0x96\n" "v_bitop3_b32 v23, v36, v49, v26 bitop3:0x96\n" "v_bitop3_b32 v11, v40, v53, v30 bitop3:0x96\n" "v_bitop3_b32 v15, v44, v25, v34 bitop3:0x96\n" "v_bitop3_b32 v19, v48, v29, v38 bitop3:0x96\n" "v_bitop3_b32 v23, v52, v33, v42 bitop3:0x96\n"
+#define PROBE_DST0 "v_bitop3_b32 v8, v24, v37, v46 bitop3:0x96\n" "v_bitop3_b32 v12, v28, v41, v50 bitop3:0x96\n" "v_bitop3_b32 v16, v32, v45, v54 bitop3:0x96\n" "v_bitop3_b32 v20, v36, v49, v26 bitop3:0x96\n" "v_bitop3_b32 v8, v40, v53, v30 bitop3:0x96\n" "v_bitop3_b32 v12, v44, v25, v34 bitop3:0x96\n" "v_bitop3_b32 v16, v48, v29, v38 bitop3:0x96\n" "v_bitop3_b32 v20, v52, v33, v42 bitop3:0x96\n" "v_bitop3_b32 v8, v24, v37, v46 bitop3:0x96\n" "v_bitop3_b32 v12, v28, v41, v50 bitop3:0x96\n" "v_bitop3_b32 v16, v32, v45, v54 bitop3:0x96\n" "v_bitop3_b32 v20, v36, v49, v26 bitop3:0x96\n" "v_bitop3_b32 v8, v40, v53, v30 bitop3:0x96\n" "v_bitop3_b32 v12, v44, v25, v34 bitop3:0x96\n" "v_bitop3_b32 v16, v48, v29, v38 bitop3:0x96\n" "v_bitop3_b32 v20, v52, v33, v42 bitop3:0x96\n"
 #define PROBE_CLOBBERS                                                                                       \
     "v8", "v9", "v10", "v11", "v12", "v13", "v14", "v15", "v16", "v17", "v18", "v19", "v20", "v21", "v22", "v23", \
         "v24", "v25", "v26", "v27", "v28", "v29", "v30", "v31", "v32", "v33", "v34", "v35", "v36", "v37", "v38",   \
@@ -136,6 +147,11 @@ __global__ void folded_stage_kernel(const uint32_t *blocks, const uint32_t *dir_
 #define PROBE_CASE(K, M)                                                                   \
     case K:                                                                                \
         for (int i = 0; i < iters; i++) asm volatile(PROBE_BLOCK(M)::: PROBE_CLOBBERS);    \
+        break;
+#define PROBE_CHAIN_BLOCK(C) C C C C C C C C
+#define PROBE_CHAIN_CASE(K, C)                                                             \
+    case K:                                                                                \
+        for (int i = 0; i < iters; i++) asm volatile(PROBE_CHAIN_BLOCK(C)::: PROBE_CLOBBERS); \
         break;
 
 // clk[6 w + 0..5] for wave w: shader-clock count before and after, real-time count before and
@@ -151,6 +167,14 @@ __global__ __launch_bounds__(256) void issue_probe_kernel(int op, int iters, uin
         PROBE_CASE(4, P_BITOP3)
         PROBE_CASE(5, P_BITOP3_SAME)
         PROBE_CASE(6, P_PERM)
+        PROBE_CHAIN_CASE(7, PROBE_CHAIN1)
+        PROBE_CHAIN_CASE(8, PROBE_CHAIN2)
+        PROBE_CHAIN_CASE(9, PROBE_CHAIN4)
+        PROBE_CHAIN_CASE(10, PROBE_CHAIN3)
+        PROBE_CHAIN_CASE(11, PROBE_CHAIN8)
+        PROBE_CHAIN_CASE(12, PROBE_CHAIN4R)
+        PROBE_CHAIN_CASE(13, PROBE_DST3)
+        PROBE_CHAIN_CASE(14, PROBE_DST0)
         default:
             break;
     }
@@ -174,10 +198,50 @@ int status() { return hipGetLastError() == hipSuccess && hipDeviceSynchronize() 
 
 }  // namespace
 
+// The folded round pair of the bitsliced kernels (generated assembly) alone, `iters` times on planes
+// made from the lane index, with the same clock and placement records as issue_probe_kernel; the
+// planes are XORed into sink so that nothing is dead.
+__global__ __launch_bounds__(256, 4) void rounds_probe_kernel(int iters, uint32_t w0, uint32_t w1, uint64_t *clk,
+                                                             uint32_t *sink) {
+    uint32_t x[32], y[32];
+    for (int q = 0; q < 32; q++) {
+        x[q] = threadIdx.x * (2 * q + 1) + blockIdx.x;
+        y[q] = (threadIdx.x ^ (0x9E3779B9u * q)) + blockIdx.x;
+    }
+    const uint64_t c0 = __builtin_readcyclecounter();
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    for (int i = 0; i < iters; i++) feistel_pair_asm<false>(x, y, w0, w1, w1, w0);
+    const uint64_t c1 = __builtin_readcyclecounter();
+    const uint64_t t1 = __builtin_amdgcn_s_memrealtime();
+    uint32_t acc = 0;
+    for (int q = 0; q < 32; q++) acc ^= x[q] ^ y[q];
+    sink[blockIdx.x * blockDim.x + threadIdx.x] = acc;
+    uint32_t hw_id, xcc_id;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_HW_ID)" : "=s"(hw_id));
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(xcc_id));
+    if (threadIdx.x % 64 == 0) {
+        const uint32_t w = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+        clk[6 * w + 0] = c0;
+        clk[6 * w + 1] = c1;
+        clk[6 * w + 2] = t0;
+        clk[6 * w + 3] = t1;
+        clk[6 * w + 4] = hw_id;
+        clk[6 * w + 5] = xcc_id;
+    }
+}
+
 // groups workgroups of 256 threads; dev_clk holds 6 * 4 * groups words.
 extern "C" int units_issue_probe(int op, int groups, int iters, uint64_t *dev_clk) {
-    if (op < 0 || op > 6 || groups < 1 || iters < 1) return -1;
+    if (op < 0 || op > 14 || groups < 1 || iters < 1) return -1;
     hipLaunchKernelGGL(issue_probe_kernel, dim3(groups), dim3(256), 0, 0, op, iters, dev_clk);
+    return status();
+}
+
+// groups workgroups of 256 threads; dev_clk: 6 * 4 * groups words; dev_sink: 256 * groups words.
+extern "C" int units_rounds_probe(int groups, int iters, uint64_t *dev_clk, uint32_t *dev_sink) {
+    if (groups < 1 || iters < 1) return -1;
+    hipLaunchKernelGGL(rounds_probe_kernel, dim3(groups), dim3(256), 0, 0, iters, 0x5A3C96E1u, 0x0F1E2D3Cu, dev_clk,
+                       dev_sink);
     return status();
 }
 
