@@ -42,7 +42,7 @@ PKG = os.path.dirname(HERE)
 SPEC = os.path.join(PKG, "csrc", "des_spec.h")
 OUT = os.path.join(PKG, "csrc", "rounds_asm.inc")
 
-FIRST_VGPR, LAST_VGPR = 8, 127     # registers the asm block may use (v0..v7 are left to the compiler)
+FIRST_VGPR, LAST_VGPR = 8, 95      # registers the asm block may use (the others stay with the compiler)
 SGPR_POOL = list(range(72, 84))    # key masks
 M32 = 0xFFFFFFFF
 
