@@ -92,6 +92,23 @@ def measured_traffic():
     return float(m_bytes.group(1))
 
 
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "tdes_ecb_kernels_1GiB_counters.md")
+
+
+def measured_issued_ops():
+    """VALU lane-operations per block that the shipped kernel issues, from the committed SQ counter
+    summary, if it was taken on the current kernel source; else None."""
+    try:
+        text = open(COUNTERS_FILE).read()
+    except OSError:
+        return None
+    m_hash = re.search(r"kernel source hash:\s*([0-9a-f]+)", text)
+    m_ops = re.search(r"issued VALU lane-ops per block:\s*([0-9.]+)", text)
+    if not m_hash or not m_ops or m_hash.group(1) != kernel_hash():
+        return None
+    return float(m_ops.group(1))
+
+
 def circuit_gates() -> int:
     """Gates in the shipped S-box circuits (sum over the eight boxes)."""
     text = open(os.path.join(PKG, "gen", "sbox_circuits.txt")).read()
@@ -429,6 +446,49 @@ def bench_paper_threads(td, torch, dev):
                         "per workgroup swept for each kernel", "rows": rows}
 
 
+def openssl_ecb_rate(keys, data):
+    """Context beside the oracle: OpenSSL's EVP_des_ede3_ecb on one host thread over the same sample
+    (GB/s), or None where libcrypto cannot be loaded."""
+    import ctypes
+    import ctypes.util
+    lib = None
+    for name in ("libcrypto.so.3", ctypes.util.find_library("crypto")):
+        if name:
+            try:
+                lib = ctypes.CDLL(name)
+                break
+            except OSError:
+                continue
+    if lib is None:
+        return None
+    vp, ip = ctypes.c_void_p, ctypes.c_int
+    lib.EVP_CIPHER_CTX_new.restype = vp
+    lib.EVP_CIPHER_CTX_free.argtypes = [vp]
+    lib.EVP_des_ede3_ecb.restype = vp
+    lib.EVP_CipherInit_ex.argtypes = [vp, vp, vp, ctypes.c_char_p, ctypes.c_char_p, ip]
+    lib.EVP_CIPHER_CTX_set_padding.argtypes = [vp, ip]
+    lib.EVP_CipherUpdate.argtypes = [vp, vp, ctypes.POINTER(ip), vp, ip]
+    lib.OpenSSL_version.restype = ctypes.c_char_p
+    lib.OpenSSL_version.argtypes = [ip]
+    out = bytearray(data.size + 16)
+    buf = (ctypes.c_uint8 * len(out)).from_buffer(out)
+    ctx = lib.EVP_CIPHER_CTX_new()
+    try:
+        if lib.EVP_CipherInit_ex(ctx, lib.EVP_des_ede3_ecb(), None, b"".join(keys), None, 1) != 1:
+            return None
+        lib.EVP_CIPHER_CTX_set_padding(ctx, 0)
+        n = ctypes.c_int(0)
+        t0 = time.perf_counter()
+        ok = lib.EVP_CipherUpdate(ctx, ctypes.addressof(buf), ctypes.byref(n), data.ctypes.data, int(data.size))
+        dt = time.perf_counter() - t0
+    finally:
+        lib.EVP_CIPHER_CTX_free(ctx)
+    if ok != 1 or n.value != data.size:
+        return None
+    return {"value": round(data.size / dt / 1e9, 6), "unit": "GB/s", "threads": 1,
+            "library": lib.OpenSSL_version(0).decode(), "sample": f"the same {data.size >> 20} MiB: {dt:.1f} s"}
+
+
 def cpu_baseline(sample_blocks, one_thread_blocks):
     """The oracle on the host's cores (every core this process may use), and on one thread."""
     import oracle
@@ -447,7 +507,8 @@ def cpu_baseline(sample_blocks, one_thread_blocks):
             "sample": f"encrypt the first {sample_blocks} blocks ({data.size >> 20} MiB) of the benchmark message "
                       f"with its key triple on {cores} threads: {dt:.1f} s",
             "one_thread": {"value": round(one.size / dt1 / 1e9, 6), "unit": "GB/s",
-                           "sample": f"the first {one_thread_blocks} blocks on 1 thread: {dt1:.1f} s"}}
+                           "sample": f"the first {one_thread_blocks} blocks on 1 thread: {dt1:.1f} s"},
+            "openssl_context": openssl_ecb_rate(keys, data)}
 
 
 def main():
@@ -514,6 +575,7 @@ def main():
     ops_per_block = 12 * gates / 8 + 120  # 48 rounds x (48 key XORs + gates + 32 XORs into L) / 32 blocks
     achieved = ops_per_block * N_BLOCKS / avg_launch_s / 1e12
     traffic = measured_traffic()
+    issued = measured_issued_ops()
     line = {
         "metric": METRIC, "value": round(value, 3), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 4), "higher_is_better": True,
@@ -526,6 +588,9 @@ def main():
                      "traffic": traffic,
                      "ops_per_block": ops_per_block, "kernel_ms": round(avg_launch_s * 1e3, 4),
                      "hbm_frac": round(16 * N_BLOCKS / avg_launch_s / 1e9 / HBM_PEAK_GBS, 4),
+                     "issued_ops_per_block": issued,
+                     "valu_frac": None if issued is None else
+                     round(issued * N_BLOCKS / avg_launch_s / 1e12 / ALU_PEAK_TOPS, 4),
                      "kernel_hash": kernel_hash()},
         "variants": variants,
         "modes": modes,
