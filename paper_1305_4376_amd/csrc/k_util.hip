@@ -10,17 +10,23 @@ namespace {
 
 constexpr int kThreads = 256;
 
-__device__ __forceinline__ uint64_t splitmix64_word(uint64_t seed, uint64_t i) {
-    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+
+// The output function applied to the state s + (i + 1) * gamma of word i.
+__device__ __forceinline__ uint64_t splitmix64_mix(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     return z ^ (z >> 31);
 }
 
+// Each thread walks its words with a fixed stride, so the state advances by stride * gamma (one
+// addition instead of a 64-bit multiplication per word).
 __global__ __launch_bounds__(kThreads) void fill_kernel(uint64_t *dev, uint64_t n, uint64_t seed, uint64_t first) {
     const uint64_t stride = (uint64_t)gridDim.x * kThreads;
-    for (uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride)
-        dev[i] = splitmix64_word(seed, first + i);
+    uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    uint64_t z = seed + (first + i + 1) * kGamma;
+    const uint64_t step = stride * kGamma;
+    for (; i < n; i += stride, z += step) dev[i] = splitmix64_mix(z);
 }
 
 }  // namespace
@@ -51,7 +57,8 @@ __global__ __launch_bounds__(kFillThreads) void fill_tiles_kernel(const tdes::Fi
     if (blockIdx.x >= n_tiles) return;
     const tdes::FillTile t = tiles[blockIdx.x];
     uint64_t *dst = reinterpret_cast<uint64_t *>(base + t.dst_off);
-    for (uint32_t i = threadIdx.x; i < t.n_words; i += kFillThreads) dst[i] = splitmix64_word(t.seed, t.first_word + i);
+    uint64_t z = t.seed + (t.first_word + threadIdx.x + 1) * kGamma;
+    for (uint32_t i = threadIdx.x; i < t.n_words; i += kFillThreads, z += kFillThreads * kGamma) dst[i] = splitmix64_mix(z);
 }
 
 }  // namespace
