@@ -352,6 +352,10 @@ typedef struct tdes_serve_config {
     uint32_t pad;
     /* Tuning of every step's batch (tdes_ctx_set_tuning); threads == 0 keeps the library's defaults for all four. */
     uint32_t threads, groups_per_cu, wave_remainder, tiles_per_draw;
+    /* Backlog-sized steps: while the queue holds more than max_inflight * max_step_blocks blocks, a
+       step may take up to (queued blocks / max_inflight) blocks, at most this many.  0, or a value
+       not above max_step_blocks: every step is capped at max_step_blocks. */
+    uint64_t backlog_step_blocks;
 } tdes_serve_config;
 
 typedef struct tdes_serve_stats {

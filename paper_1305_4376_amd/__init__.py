@@ -55,7 +55,8 @@ class _ServeConfig(ctypes.Structure):
                 ("max_step_jobs", ctypes.c_uint32), ("max_step_blocks", ctypes.c_uint64),
                 ("keep_outputs", ctypes.c_uint32), ("pad", ctypes.c_uint32),
                 ("threads", ctypes.c_uint32), ("groups_per_cu", ctypes.c_uint32),
-                ("wave_remainder", ctypes.c_uint32), ("tiles_per_draw", ctypes.c_uint32)]
+                ("wave_remainder", ctypes.c_uint32), ("tiles_per_draw", ctypes.c_uint32),
+                ("backlog_step_blocks", ctypes.c_uint64)]
 
 
 class _ServeStats(ctypes.Structure):
@@ -348,11 +349,12 @@ def tdes_ctx_get_info(ctx: int) -> dict:
 
 def tdes_server_create(dev_sched_table, n_scheds: int, budget_bytes: int, max_inflight: int = 2,
                        max_step_jobs: int = 4096, max_step_blocks: int = 1 << 26, keep_outputs: bool = False,
-                       tuning=None) -> int:
+                       tuning=None, backlog_step_blocks: int = 0) -> int:
     """Start a serving engine over a resident schedule table; returns an opaque handle.  tuning: the
     batch shape (threads, groups_per_cu, wave_remainder, tiles_per_draw) of every step, None for the
     library's defaults, or "cached" for the shape the autotuner recorded for servers with this step
-    size on this GPU (the defaults if none)."""
+    size on this GPU (the defaults if none).  backlog_step_blocks: the largest step while the queue
+    is long (see tdes_serve_config); 0 keeps every step at max_step_blocks."""
     _need(dev_sched_table, int(n_scheds) * TDES_SCHED_BYTES, "schedule table")
     if isinstance(tuning, str):
         if tuning != "cached":
@@ -363,7 +365,7 @@ def tdes_server_create(dev_sched_table, n_scheds: int, budget_bytes: int, max_in
     if len(t) != 4:
         raise ValueError("tuning is (threads, groups_per_cu, wave_remainder, tiles_per_draw)")
     cfg = _ServeConfig(int(budget_bytes), int(max_inflight), int(max_step_jobs), int(max_step_blocks),
-                       int(bool(keep_outputs)), 0, *t)
+                       int(bool(keep_outputs)), 0, *t, int(backlog_step_blocks))
     h = ctypes.c_void_p()
     _check(load_library().tdes_server_create(ctypes.byref(h), ctypes.byref(cfg), _ptr(dev_sched_table),
                                              int(n_scheds)), "tdes_server_create")

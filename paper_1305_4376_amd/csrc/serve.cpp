@@ -144,6 +144,7 @@ struct tdes_server {
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<uint64_t> pending;
+    uint64_t pending_blocks = 0;  // blocks of the queued requests that are not canceled
     std::unordered_map<uint64_t, Request> reqs;
     std::deque<tdes_completion> completed;
     uint64_t next_id = 1;
@@ -215,6 +216,12 @@ size_t admit(tdes_server *s, Step &st) {
     std::lock_guard<std::mutex> lk(s->mu);
     const double t = s->now();
     uint64_t blocks = 0;
+    // A long queue is served in larger steps: up to its share per step in flight, within the backlog cap.
+    uint64_t cap = s->cfg.max_step_blocks;
+    if (s->cfg.backlog_step_blocks > cap) {
+        const uint64_t share = s->pending_blocks / s->cfg.max_inflight;
+        if (share > cap) cap = share < s->cfg.backlog_step_blocks ? share : s->cfg.backlog_step_blocks;
+    }
     while (!s->pending.empty() && st.ids.size() < s->cfg.max_step_jobs) {
         const uint64_t id = s->pending.front();
         auto it = s->reqs.find(id);
@@ -223,7 +230,7 @@ size_t admit(tdes_server *s, Step &st) {
             continue;
         }
         Request &r = it->second;
-        if (!st.ids.empty() && blocks + r.r.n_blocks > s->cfg.max_step_blocks) break;
+        if (!st.ids.empty() && blocks + r.r.n_blocks > cap) break;
         uint64_t in_off, out_off;
         if (!s->pool.alloc(r.bytes, &in_off)) break;  // first come, first served: wait for memory
         if (!s->pool.alloc(r.bytes, &out_off)) {
@@ -231,6 +238,7 @@ size_t admit(tdes_server *s, Step &st) {
             break;
         }
         s->pending.pop_front();
+        s->pending_blocks -= r.r.n_blocks;
         r.in_off = in_off;
         r.out_off = out_off;
         r.admitted = true;
@@ -457,6 +465,7 @@ static int submit_at(tdes_server *s, const tdes_request *r, double t_arrival, ui
     q.bytes = bytes;
     s->reqs.emplace(id, q);
     s->pending.push_back(id);
+    s->pending_blocks += r->n_blocks;
     s->outstanding++;
     s->stats.submitted++;
     if (id_out) *id_out = id;
@@ -476,6 +485,7 @@ extern "C" int tdes_server_cancel(tdes_server *s, uint64_t id) {
     if (it == s->reqs.end() || it->second.admitted || it->second.canceled) return TDES_ERR_STATE;
     Request &r = it->second;
     r.canceled = true;
+    s->pending_blocks -= r.r.n_blocks;
     r.t_done = s->now();
     s->stats.canceled++;
     complete_locked(s, id, r, TDES_ERR_STATE);

@@ -137,6 +137,31 @@ def test_tuned_steps_every_block(table):
         _check_oracle(keys, reqs[i], mixed[i])
 
 
+def test_backlog_steps_every_block(table):
+    """A long queue served in larger steps (backlog_step_blocks): fewer steps than with the fixed step
+    cap on the same trace, and every block of every request still equal to the oracle and to the
+    fixed-cap run."""
+    keys, dev_table = table
+    reqs = _requests(160, 0x5E2B, max_blocks=1 << 16)
+    arrival = np.zeros(reqs.size)
+    outs, steps = [], []
+    for backlog in (0, 1 << 20):
+        server = td.tdes_server_create(dev_table, N_KEYS, 1 << 30, max_inflight=2, max_step_jobs=4096,
+                                       max_step_blocks=1 << 16, keep_outputs=True, backlog_step_blocks=backlog)
+        try:
+            print(f"[serve] backlog steps: cap {backlog}, {reqs.size} requests at once", flush=True)
+            done = td.tdes_server_run_trace(server, reqs, arrival)
+            assert (done["status"] == 0).all()
+            steps.append(td.tdes_server_stats(server)["steps"])
+            outs.append(_outputs_by_tag(server, done, reqs))
+        finally:
+            td.tdes_server_destroy(server)
+    assert steps[1] < steps[0], steps
+    for i in range(reqs.size):
+        assert np.array_equal(outs[0][i], outs[1][i]), i
+        _check_oracle(keys, reqs[i], outs[1][i])
+
+
 def test_server_rejects_bad_tuning(table):
     _, dev_table = table
     for kw in ({"tuning": (96, 4, 0, 0)}, {"tuning": (256, 4, 4096, 0)}, {"tuning": (256, 4, 0, 17)}):

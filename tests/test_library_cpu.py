@@ -156,9 +156,10 @@ def test_struct_layouts_match_the_header(tmp_path):
     src = tmp_path / "sizes.c"
     src.write_text(
         '#include <stdio.h>\n#include <stddef.h>\n#include "tdes.h"\n'
-        'int main(void) { printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(tdes_job), sizeof(tdes_batch_info),'
+        'int main(void) { printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(tdes_job), sizeof(tdes_batch_info),'
         ' sizeof(tdes_request), sizeof(tdes_completion), sizeof(tdes_serve_config), sizeof(tdes_serve_stats),'
-        ' offsetof(tdes_request, host_out), offsetof(tdes_completion, t_complete), sizeof(tdes_sched)); return 0; }\n')
+        ' offsetof(tdes_request, host_out), offsetof(tdes_completion, t_complete), sizeof(tdes_sched),'
+        ' offsetof(tdes_serve_config, backlog_step_blocks)); return 0; }\n')
     exe = tmp_path / "sizes"
     import subprocess
     subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)])
@@ -166,7 +167,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     import ctypes as ct
     want = [td.JOB_DTYPE.itemsize, ct.sizeof(td._BatchInfo), td.REQUEST_DTYPE.itemsize, td.COMPLETION_DTYPE.itemsize,
             ct.sizeof(td._ServeConfig), ct.sizeof(td._ServeStats), td.REQUEST_DTYPE.fields["host_out"][1],
-            td.COMPLETION_DTYPE.fields["t_complete"][1], td.TDES_SCHED_BYTES]
+            td.COMPLETION_DTYPE.fields["t_complete"][1], td.TDES_SCHED_BYTES, td._ServeConfig.backlog_step_blocks.offset]
     assert got == want
 
 
