@@ -317,9 +317,12 @@ int tdes_ecb_batch_static(const tdes_job *dev_jobs, uint32_t n_jobs, const void 
 /* ---- serving: continuous batching of requests under resident keys ---- */
 
 /* A request.  Its input is n_blocks * 8 bytes: copied from host_in when that
- * is not NULL, otherwise generated on the device as words 0.. of the
- * SplitMix64 stream seeded with `seed` (see tdes_fill_splitmix64).  If host_out
- * is not NULL the output is copied there before the request completes. */
+ * is not NULL, otherwise generated on the device from `seed`: block i, with
+ * i = 256 * (64 * c + k) + t (t < 256, k < 64), is the little-endian word
+ * X^k(W), where W is word 16384 * c + t of the SplitMix64 stream seeded with
+ * `seed` (see tdes_fill_splitmix64) and X the xorshift64 step
+ * x ^= x << 13, x ^= x >> 7, x ^= x << 17 (Marsaglia, 2003).  If host_out is
+ * not NULL the output is copied there before the request completes. */
 typedef struct tdes_request {
     uint64_t n_blocks;     /* 1 .. 2^32 */
     uint32_t key_id;       /* index into the server's resident schedule table */

@@ -66,7 +66,8 @@ hipError_t launch_cbc_decrypt(const uint32_t *ks, const uint8_t *in, uint8_t *ou
 hipError_t launch_fill_splitmix64(uint64_t *dev, uint64_t n_words, uint64_t seed, uint64_t first,
                                   hipStream_t stream);
 
-// A run of SplitMix64 words written to base + dst_off (one workgroup each).
+// A run of serving-payload words (chained generator, k_util.hip) written to base + dst_off, one
+// workgroup each; first_word is the run's first word in its request, a multiple of 16384.
 struct FillTile {
     uint64_t dst_off;
     uint64_t seed;

@@ -284,7 +284,7 @@ int launch_step(tdes_server *s, Step &st) {
             st.jobs.push_back(j);
         }
     }
-    // Inputs: host payloads are copied in; the others come from each request's SplitMix64 stream.
+    // Inputs: host payloads are copied in; the others are generated from each request's seed.
     for (size_t i = 0; i < st.ids.size(); i++) {
         const tdes_request &rq = st.rq[i];
         const tdes_job &j = st.jobs[i];

@@ -11,7 +11,13 @@ Recipe:
   * message block i is the 8 little-endian bytes of word i;
   * a key triple is 24 bytes taken the same way from a key seed, each byte's
     least significant bit then set so that the byte has odd parity (the
-    standard's parity convention; the cipher ignores these bits).
+    standard's parity convention; the cipher ignores these bits);
+  * a served request's payload (made on the device when it is admitted) takes
+    the stream's words as chain heads: word i = 256 * (64 * c + k) + t
+    (t < 256, k < 64) is X^k(SplitMix64 word 16384 * c + t), X the xorshift64
+    step (Marsaglia, "Xorshift RNGs", J. Stat. Softw. 8(14), 2003, shifts
+    13, 7, 17), which costs the device three shifts and XORs per word instead
+    of two 64-bit multiplications.
 
 The device-side generator in the library implements the same published
 definition on its own; tests compare the two.
@@ -49,6 +55,44 @@ def splitmix64_at(seed: int, indices: np.ndarray) -> np.ndarray:
         z = (z ^ (z >> np.uint64(27))) * _M2
         z = z ^ (z >> np.uint64(31))
     return z
+
+
+PAYLOAD_COLUMNS = 256
+PAYLOAD_CHAIN = 64
+
+
+def xorshift64(x: np.ndarray) -> np.ndarray:
+    """One xorshift64 step (shifts 13, 7, 17) on each 64-bit word."""
+    x = x ^ (x << np.uint64(13))
+    x = x ^ (x >> np.uint64(7))
+    return x ^ (x << np.uint64(17))
+
+
+def payload_words_at(seed: int, indices) -> np.ndarray:
+    """Words at the given indices of a served request's payload (chain heads from the SplitMix64
+    stream, each following word one xorshift64 step on from the one 256 before it in its chain)."""
+    i = np.asarray(indices, dtype=np.uint64)
+    col = i % np.uint64(PAYLOAD_COLUMNS)
+    row = i // np.uint64(PAYLOAD_COLUMNS)
+    step = (row % np.uint64(PAYLOAD_CHAIN)).astype(np.int64)
+    head = (row // np.uint64(PAYLOAD_CHAIN)) * np.uint64(PAYLOAD_COLUMNS * PAYLOAD_CHAIN) + col
+    x = splitmix64_at(seed, head)
+    for k in range(1, PAYLOAD_CHAIN):
+        x = np.where(step >= k, xorshift64(x), x)
+    return x
+
+
+def payload(seed: int, n_blocks: int) -> np.ndarray:
+    """A served request's n_blocks-block payload (uint8 array of 8*n_blocks)."""
+    span = PAYLOAD_COLUMNS * PAYLOAD_CHAIN
+    chains = -(-n_blocks // span)
+    w = np.empty((chains, PAYLOAD_CHAIN, PAYLOAD_COLUMNS), dtype=np.uint64)
+    heads = (np.arange(chains, dtype=np.uint64)[:, None] * np.uint64(span)
+             + np.arange(PAYLOAD_COLUMNS, dtype=np.uint64)[None, :])
+    w[:, 0, :] = splitmix64_at(seed, heads)
+    for k in range(1, PAYLOAD_CHAIN):
+        w[:, k, :] = xorshift64(w[:, k - 1, :])
+    return w.reshape(-1)[:n_blocks].astype("<u8").view(np.uint8)
 
 
 def message(seed: int, n_blocks: int, first_block: int = 0) -> np.ndarray:

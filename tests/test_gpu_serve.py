@@ -69,10 +69,10 @@ def _copy_dev(dst, src, nbytes):
 
 
 def _check_oracle(keys, req, out):
-    """Every block of a request's output against the oracle on its payload (the request's SplitMix64 stream)."""
+    """Every block of a request's output against the oracle on its payload (generated from the request's seed)."""
     n = int(req["n_blocks"])
     k = keys[req["key_id"]]
-    src = inputs.message(int(req["seed"]), n)
+    src = inputs.payload(int(req["seed"]), n)
     want = _gpu.oracle_on_blocks((k[:8].tobytes(), k[8:16].tobytes(), k[16:].tobytes()), src,
                                  decrypt=bool(req["direction"]))
     assert out.size == want.size

@@ -51,3 +51,35 @@ def test_log_uniform_lengths():
     assert n.min() >= 1 and n.max() <= 131072
     med = np.median(n)
     assert 150 < med < 900  # exp(ln(131073)/2) ~ 362
+
+
+def _payload_sequential(seed, count):
+    # Column t of the payload (words t, t + 256, ...) walks chains of 64 words: each chain opens with
+    # the SplitMix64 word at its own index, and each later word is one xorshift64 step on.
+    stream = _splitmix64_sequential(seed, count)
+    out = [0] * count
+    for t in range(min(256, count)):
+        x = 0
+        for row, i in enumerate(range(t, count, 256)):
+            if row % 64 == 0:
+                x = stream[i]
+            else:
+                x ^= (x << 13) & MASK
+                x ^= x >> 7
+                x ^= (x << 17) & MASK
+            out[i] = x
+    return out
+
+
+def test_payload_chains():
+    """Served payloads: chain heads are the stream's words, the rest xorshift64 successors; slices
+    and sampled indices agree with the whole; no repeated word in a 2^20-word payload."""
+    n = 3 * 16384 + 777                     # three whole chains per column, a partial fourth
+    want = _payload_sequential(0x5E000001, n)
+    got = inputs.payload(0x5E000001, n).view("<u8")
+    assert [int(v) for v in got] == want
+    idx = np.array([0, 255, 256, 16383, 16384, 16384 + 300, n - 1])
+    assert [int(v) for v in inputs.payload_words_at(0x5E000001, idx)] == [want[i] for i in idx]
+    big = inputs.payload(17, 1 << 20).view("<u8")
+    assert np.unique(big).size == big.size
+    assert int(big[0]) == int(inputs.splitmix64(17, 0, 1)[0])
