@@ -250,11 +250,12 @@ def bench_serving(td, torch, inputs, dev, batch_capacity_bps, seconds, tuning=No
                 "failed": int((~ok).sum()), "steps": stats["steps"],
                 "peak_pool_gib": round(stats["peak_pool_bytes"] / 2 ** 30, 3)}
 
-    # Saturation: 20000 requests (about 31 GB of payload) all arriving at t = 0, for each batch shape
-    # of the server's steps (the library's default and the one tuned on the batched workload); the
-    # fastest is kept for the loads.
+    # Saturation: 100000 requests (about 157 GB of payload, long enough that filling and draining the
+    # step pipeline weigh little) all arriving at t = 0, for each batch shape of the server's steps
+    # (the library's default and the one tuned on the batched workload); the fastest is kept for the
+    # loads.
     from paper_1305_4376_amd import autotune
-    sat_trace = trace(0x5E50, 20000, 0.0)
+    sat_trace = trace(0x5E50, 100000, 0.0)
     candidates = {}
 
     def saturated(sh):

@@ -65,6 +65,7 @@ struct tdes_ctx {
     uint32_t groups_per_cu = 4;
     uint32_t wave_remainder = kDefaultWaveRemainder;  // remainders this long take a wave tile
     uint32_t tiles_per_draw = 1;                      // tiles a wave takes per counter draw
+    bool capped = false;                              // launch the 120-VGPR kernel variant
     // Captured graph and what it was captured for.
     hipGraphExec_t exec = nullptr;
     const void *g_sched = nullptr;
@@ -72,6 +73,7 @@ struct tdes_ctx {
     const void *g_tiles = nullptr;  // every pointer the kernel node was captured with
     const void *g_slots = nullptr;
     uint32_t g_grid = 0, g_threads = 0, g_draw = 0;
+    bool g_capped = false;
     tdes_batch_info info{};
 };
 
@@ -222,11 +224,12 @@ int launch_plan(tdes_ctx *c, const void *sched, uint8_t *base, bool use_graph, h
     const uint32_t *ks = static_cast<const uint32_t *>(sched);
     if (!use_graph) {
         if (tdes::launch_batch(ks, hdr, tiles, slots, c->d_counter, base, grid, c->threads, c->tiles_per_draw,
-                               stream) != hipSuccess)
+                               c->capped, stream) != hipSuccess)
             return TDES_ERR_HIP;
     } else {
         if (!c->exec || c->g_sched != sched || c->g_base != base || c->g_tiles != tiles || c->g_slots != slots ||
-            c->g_grid != grid || c->g_threads != c->threads || c->g_draw != c->tiles_per_draw) {
+            c->g_grid != grid || c->g_threads != c->threads || c->g_draw != c->tiles_per_draw ||
+            c->g_capped != c->capped) {
             if (c->exec) {
                 (void)hipGraphExecDestroy(c->exec);
                 c->exec = nullptr;
@@ -235,7 +238,7 @@ int launch_plan(tdes_ctx *c, const void *sched, uint8_t *base, bool use_graph, h
             if (hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
                 return TDES_ERR_HIP;
             const hipError_t le = tdes::launch_batch(ks, hdr, tiles, slots, c->d_counter, base, grid, c->threads,
-                                                     c->tiles_per_draw, c->capture_stream);
+                                                     c->tiles_per_draw, c->capped, c->capture_stream);
             const hipError_t ce = hipStreamEndCapture(c->capture_stream, &graph);
             if (le != hipSuccess || ce != hipSuccess || !graph) {
                 if (graph) (void)hipGraphDestroy(graph);
@@ -254,6 +257,7 @@ int launch_plan(tdes_ctx *c, const void *sched, uint8_t *base, bool use_graph, h
             c->g_grid = grid;
             c->g_threads = c->threads;
             c->g_draw = c->tiles_per_draw;
+            c->g_capped = c->capped;
             c->info.graph_captures++;
         }
         if (hipGraphLaunch(c->exec, stream) != hipSuccess) return TDES_ERR_HIP;
@@ -328,6 +332,10 @@ extern "C" int tdes_ctx_set_tuning(tdes_ctx *c, uint32_t threads, uint32_t group
     c->info.tiles_per_draw = c->tiles_per_draw;
     return TDES_OK;
 }
+
+namespace tdes {
+void ctx_set_capped(tdes_ctx *c, bool capped) { c->capped = capped; }
+}  // namespace tdes
 
 extern "C" int tdes_ctx_get_info(const tdes_ctx *c, tdes_batch_info *info) {
     if (!c || !info) return TDES_ERR_NULL;

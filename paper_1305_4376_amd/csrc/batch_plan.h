@@ -28,8 +28,9 @@ static_assert(sizeof(Slot) == 32, "slot is 32 bytes");
 // Tile word: index of its first slot; the top bit marks a lane tile (64 slots).
 constexpr uint32_t kLaneTileBit = 0x80000000u;
 
+// capped: the variant held to 120 VGPRs (room for another kernel's waves beside it).
 hipError_t launch_batch(const uint32_t *sched, const PlanHeader *hdr, const uint32_t *tiles, const Slot *slots,
                         uint32_t *counter, uint8_t *base, uint32_t grid, uint32_t threads, uint32_t tiles_per_draw,
-                        hipStream_t stream);
+                        bool capped, hipStream_t stream);
 
 }  // namespace tdes

@@ -66,6 +66,10 @@ hipError_t launch_cbc_decrypt(const uint32_t *ks, const uint8_t *in, uint8_t *ou
 hipError_t launch_fill_splitmix64(uint64_t *dev, uint64_t n_words, uint64_t seed, uint64_t first,
                                   hipStream_t stream);
 
+// Batch contexts of the server launch the 120-VGPR variant of the batch kernel, so that the
+// payload fills of later steps run beside it.
+void ctx_set_capped(tdes_ctx *c, bool capped);
+
 // A run of serving-payload words (chained generator, k_util.hip) written to base + dst_off, one
 // workgroup each; first_word is the run's first word in its request, a multiple of 16384.
 struct FillTile {
@@ -75,7 +79,7 @@ struct FillTile {
     uint32_t n_words;
     uint32_t pad;
 };
-constexpr uint32_t kFillTileWords = 1u << 16;
+constexpr uint32_t kFillTileWords = 1u << 18;
 hipError_t launch_fill_tiles(const FillTile *tiles, uint32_t n_tiles, uint8_t *base, hipStream_t stream);
 
 }  // namespace tdes

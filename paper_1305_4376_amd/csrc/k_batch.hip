@@ -57,9 +57,9 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-__global__ __launch_bounds__(kMaxThreads, kMinGroupsPerCU) void tdes_batch_kernel(
-    const uint32_t *__restrict__ sched, const tdes::PlanHeader *__restrict__ hdr, const uint32_t *__restrict__ tiles,
-    const tdes::Slot *__restrict__ slots, uint32_t *counter, uint8_t *base, uint32_t per_draw) {
+__device__ __forceinline__ void batch_waves(const uint32_t *__restrict__ sched, const tdes::PlanHeader *__restrict__ hdr,
+                                            const uint32_t *__restrict__ tiles, const tdes::Slot *__restrict__ slots,
+                                            uint32_t *counter, uint8_t *base, uint32_t per_draw) {
     const uint32_t lane = threadIdx.x % kLanes;
     const uint32_t n_tiles = hdr->n_tiles;
     const uint32_t n_slots = hdr->n_slots;
@@ -103,17 +103,39 @@ __global__ __launch_bounds__(kMaxThreads, kMinGroupsPerCU) void tdes_batch_kerne
     }
 }
 
+__global__ __launch_bounds__(kMaxThreads, kMinGroupsPerCU) void tdes_batch_kernel(
+    const uint32_t *__restrict__ sched, const tdes::PlanHeader *__restrict__ hdr, const uint32_t *__restrict__ tiles,
+    const tdes::Slot *__restrict__ slots, uint32_t *counter, uint8_t *base, uint32_t per_draw) {
+    batch_waves(sched, hdr, tiles, slots, counter, base, per_draw);
+}
+
+// The same waves held to 120 VGPRs instead of 128 (on this target the attribute counts the unified
+// VGPR/AGPR budget in pairs: 60 -> 120 registers; no AGPR is used).  Four such waves per SIMD leave
+// 32 registers free, room for two waves of a small kernel on another stream (the server's payload
+// fill) to run beside the persistent cipher instead of waiting for its workgroups to retire.  A few
+// more values spill in the tile load and store phases.
+__global__ __launch_bounds__(kMaxThreads, kMinGroupsPerCU) __attribute__((amdgpu_num_vgpr(60))) void
+tdes_batch_kernel_capped(const uint32_t *__restrict__ sched, const tdes::PlanHeader *__restrict__ hdr,
+                         const uint32_t *__restrict__ tiles, const tdes::Slot *__restrict__ slots, uint32_t *counter,
+                         uint8_t *base, uint32_t per_draw) {
+    batch_waves(sched, hdr, tiles, slots, counter, base, per_draw);
+}
+
 }  // namespace
 
 namespace tdes {
 
 hipError_t launch_batch(const uint32_t *sched, const PlanHeader *hdr, const uint32_t *tiles, const Slot *slots,
                         uint32_t *counter, uint8_t *base, uint32_t grid, uint32_t threads, uint32_t tiles_per_draw,
-                        hipStream_t stream) {
+                        bool capped, hipStream_t stream) {
     if (threads == 0 || threads > kMaxThreads || threads % kLanes != 0 || grid == 0 || tiles_per_draw == 0)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(tdes_batch_kernel, dim3(grid), dim3(threads), 0, stream, sched, hdr, tiles, slots, counter,
-                       base, tiles_per_draw);
+    if (capped)
+        hipLaunchKernelGGL(tdes_batch_kernel_capped, dim3(grid), dim3(threads), 0, stream, sched, hdr, tiles, slots,
+                           counter, base, tiles_per_draw);
+    else
+        hipLaunchKernelGGL(tdes_batch_kernel, dim3(grid), dim3(threads), 0, stream, sched, hdr, tiles, slots, counter,
+                           base, tiles_per_draw);
     return hipGetLastError();
 }
 

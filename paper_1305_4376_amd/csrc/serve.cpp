@@ -430,6 +430,7 @@ extern "C" int tdes_server_create(tdes_server **out, const tdes_serve_config *cf
             delete s;
             return TDES_ERR_HIP;
         }
+        tdes::ctx_set_capped(st.ctx, true);
     }
     s->engine = std::thread(engine_loop, s);
     *out = s;
