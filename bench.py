@@ -202,7 +202,7 @@ def bench_batched(td, torch, inputs, dev, reps=10, cache=None):
 
 
 def bench_serving(td, torch, inputs, dev, batch_capacity_bps, seconds, tuning=None, cache=None, step_blocks=1 << 24,
-                  backlog_step_blocks=1 << 25):
+                  backlog_step_blocks=1 << 25, in_flight=3):
     """C5: Poisson arrivals, sizes log-uniform 512 B .. 16 MiB, 50/50 directions, 65536 resident triples,
     64 GiB admission budget.  The batch shape of the server's steps is chosen by its saturated
     throughput (every request of a trace arriving at once).  Offered loads: 0.5 / 0.8 / 0.95 of the batched workload's capacity (graph
@@ -224,7 +224,7 @@ def bench_serving(td, torch, inputs, dev, batch_capacity_bps, seconds, tuning=No
         return reqs, arrival
 
     def run(reqs, arrival, shape=None):
-        server = td.tdes_server_create(table, n_keys, 64 << 30, max_inflight=3, max_step_jobs=4096,
+        server = td.tdes_server_create(table, n_keys, 64 << 30, max_inflight=in_flight, max_step_jobs=4096,
                                        max_step_blocks=step_blocks, tuning=shape,
                                        backlog_step_blocks=backlog_step_blocks)
         try:
@@ -275,7 +275,7 @@ def bench_serving(td, torch, inputs, dev, batch_capacity_bps, seconds, tuning=No
     return {"workload": "Poisson arrivals, 512 B..16 MiB log-uniform, 50/50 encrypt/decrypt, 65536 resident "
                         "3-key triples, 64 GiB budget, payloads generated on the device at admission; latency = "
                         "host-observed completion - scheduled arrival; each trace after a warm-up of 5% of it",
-            "steps": {"in_flight": 3, "max_step_blocks": step_blocks, "backlog_step_blocks": backlog_step_blocks},
+            "steps": {"in_flight": in_flight, "max_step_blocks": step_blocks, "backlog_step_blocks": backlog_step_blocks},
             "tuning": list(shape) if shape else "default",
             "saturated_gbs_by_shape": {("x".join(map(str, sh)) if sh else "default"): r["delivered_gbs"]
                                        for sh, r in candidates.items()},

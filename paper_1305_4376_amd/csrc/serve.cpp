@@ -21,6 +21,11 @@
 //      requests are not starved), up to the per-step job and block limits;
 //   3. launch the step: generate or copy the inputs, one batched cipher
 //      launch, copy out host outputs, record the step's event.
+//
+// The steps' batch contexts launch the 120-VGPR variant of the batch kernel:
+// beside its four waves per SIMD the payload fills of the next steps find
+// registers to run in, instead of waiting for a batch kernel's workgroups to
+// retire (the fills then no longer sit between two steps' ciphers).
 #include <stdint.h>
 #include <string.h>
 
