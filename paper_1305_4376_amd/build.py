@@ -25,7 +25,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include")]
 
-SOURCES = ["api.cpp", "keysched.cpp", "batch.cpp", "serve.cpp", "host_path.cpp", "k_table.hip", "k_bitslice.hip", "k_batch.hip", "k_static.hip", "k_util.hip"]
+SOURCES = ["api.cpp", "keysched.cpp", "batch.cpp", "serve.cpp", "host_path.cpp", "k_table.hip", "k_bitslice.hip", "k_batch.hip", "k_batch_capped.hip", "k_static.hip", "k_util.hip"]
 
 
 def _run(cmd, verbose):

@@ -32,5 +32,9 @@ constexpr uint32_t kLaneTileBit = 0x80000000u;
 hipError_t launch_batch(const uint32_t *sched, const PlanHeader *hdr, const uint32_t *tiles, const Slot *slots,
                         uint32_t *counter, uint8_t *base, uint32_t grid, uint32_t threads, uint32_t tiles_per_draw,
                         bool capped, hipStream_t stream);
+// The capped variant alone (k_batch_capped.hip); arguments checked by launch_batch.
+hipError_t launch_batch_capped(const uint32_t *sched, const PlanHeader *hdr, const uint32_t *tiles, const Slot *slots,
+                               uint32_t *counter, uint8_t *base, uint32_t grid, uint32_t threads,
+                               uint32_t tiles_per_draw, hipStream_t stream);
 
 }  // namespace tdes

@@ -57,9 +57,25 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-__device__ __forceinline__ void batch_waves(const uint32_t *__restrict__ sched, const tdes::PlanHeader *__restrict__ hdr,
-                                            const uint32_t *__restrict__ tiles, const tdes::Slot *__restrict__ slots,
-                                            uint32_t *counter, uint8_t *base, uint32_t per_draw) {
+// The server's steps launch the same kernel held to 120 VGPRs instead of 128
+// (k_batch_capped.hip builds this file with TDES_BATCH_CAPPED defined; on this
+// target the attribute counts the unified VGPR/AGPR budget in pairs: 60 -> 120
+// registers, no AGPR is used).  Four such waves per SIMD leave 32 registers
+// free, room for two waves of a small kernel on another stream (the server's
+// payload fill) to run beside the persistent cipher instead of waiting for its
+// workgroups to retire; a few more values spill in the tile load and store
+// phases.  Each variant is built in a translation unit of its own: with both in
+// one, the uncapped kernel's code moved and ran the C4 batch 2% slower.
+#ifdef TDES_BATCH_CAPPED
+#define TDES_BATCH_KERNEL \
+    __global__ __launch_bounds__(kMaxThreads, kMinGroupsPerCU) __attribute__((amdgpu_num_vgpr(60))) void tdes_batch_kernel_capped
+#else
+#define TDES_BATCH_KERNEL __global__ __launch_bounds__(kMaxThreads, kMinGroupsPerCU) void tdes_batch_kernel
+#endif
+
+TDES_BATCH_KERNEL(const uint32_t *__restrict__ sched, const tdes::PlanHeader *__restrict__ hdr,
+                  const uint32_t *__restrict__ tiles, const tdes::Slot *__restrict__ slots, uint32_t *counter,
+                  uint8_t *base, uint32_t per_draw) {
     const uint32_t lane = threadIdx.x % kLanes;
     const uint32_t n_tiles = hdr->n_tiles;
     const uint32_t n_slots = hdr->n_slots;
@@ -103,40 +119,29 @@ __device__ __forceinline__ void batch_waves(const uint32_t *__restrict__ sched, 
     }
 }
 
-__global__ __launch_bounds__(kMaxThreads, kMinGroupsPerCU) void tdes_batch_kernel(
-    const uint32_t *__restrict__ sched, const tdes::PlanHeader *__restrict__ hdr, const uint32_t *__restrict__ tiles,
-    const tdes::Slot *__restrict__ slots, uint32_t *counter, uint8_t *base, uint32_t per_draw) {
-    batch_waves(sched, hdr, tiles, slots, counter, base, per_draw);
-}
-
-// The same waves held to 120 VGPRs instead of 128 (on this target the attribute counts the unified
-// VGPR/AGPR budget in pairs: 60 -> 120 registers; no AGPR is used).  Four such waves per SIMD leave
-// 32 registers free, room for two waves of a small kernel on another stream (the server's payload
-// fill) to run beside the persistent cipher instead of waiting for its workgroups to retire.  A few
-// more values spill in the tile load and store phases.
-__global__ __launch_bounds__(kMaxThreads, kMinGroupsPerCU) __attribute__((amdgpu_num_vgpr(60))) void
-tdes_batch_kernel_capped(const uint32_t *__restrict__ sched, const tdes::PlanHeader *__restrict__ hdr,
-                         const uint32_t *__restrict__ tiles, const tdes::Slot *__restrict__ slots, uint32_t *counter,
-                         uint8_t *base, uint32_t per_draw) {
-    batch_waves(sched, hdr, tiles, slots, counter, base, per_draw);
-}
-
 }  // namespace
 
 namespace tdes {
 
+#ifdef TDES_BATCH_CAPPED
+hipError_t launch_batch_capped(const uint32_t *sched, const PlanHeader *hdr, const uint32_t *tiles, const Slot *slots,
+                               uint32_t *counter, uint8_t *base, uint32_t grid, uint32_t threads,
+                               uint32_t tiles_per_draw, hipStream_t stream) {
+    hipLaunchKernelGGL(tdes_batch_kernel_capped, dim3(grid), dim3(threads), 0, stream, sched, hdr, tiles, slots,
+                       counter, base, tiles_per_draw);
+    return hipGetLastError();
+}
+#else
 hipError_t launch_batch(const uint32_t *sched, const PlanHeader *hdr, const uint32_t *tiles, const Slot *slots,
                         uint32_t *counter, uint8_t *base, uint32_t grid, uint32_t threads, uint32_t tiles_per_draw,
                         bool capped, hipStream_t stream) {
     if (threads == 0 || threads > kMaxThreads || threads % kLanes != 0 || grid == 0 || tiles_per_draw == 0)
         return hipErrorInvalidValue;
-    if (capped)
-        hipLaunchKernelGGL(tdes_batch_kernel_capped, dim3(grid), dim3(threads), 0, stream, sched, hdr, tiles, slots,
-                           counter, base, tiles_per_draw);
-    else
-        hipLaunchKernelGGL(tdes_batch_kernel, dim3(grid), dim3(threads), 0, stream, sched, hdr, tiles, slots, counter,
-                           base, tiles_per_draw);
+    if (capped) return launch_batch_capped(sched, hdr, tiles, slots, counter, base, grid, threads, tiles_per_draw, stream);
+    hipLaunchKernelGGL(tdes_batch_kernel, dim3(grid), dim3(threads), 0, stream, sched, hdr, tiles, slots, counter,
+                       base, tiles_per_draw);
     return hipGetLastError();
 }
+#endif
 
 }  // namespace tdes
