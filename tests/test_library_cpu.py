@@ -329,3 +329,14 @@ def test_ctx_create_rejects_a_missing_device():
     rc = lib.tdes_ctx_create(ctypes.byref(h), 1 << 20)
     assert rc in (-7, -8) and not h.value     # -8 where the runtime cannot count devices at all
     assert lib.tdes_ctx_create(None, 0) == -1
+
+
+def test_library_embeds_every_kernel():
+    """The built library carries the gfx950 code of every kernel its launchers start (the kernel
+    names appear in the embedded code objects): a source left out of the build, or a kernel lost to
+    a preprocessor branch, fails here rather than at launch."""
+    data = open(td.library_path(), "rb").read()
+    for name in (b"tdes_bitslice_kernel", b"tdes_bitslice_tail_kernel", b"tdes_table_kernel", b"tdes_batch_kernel",
+                 b"tdes_batch_kernel_capped", b"tdes_static_plan_kernel", b"tdes_static_batch_kernel", b"fill_kernel", b"fill_tiles_kernel"):
+        assert name in data, name
+    assert b"gfx950" in data
