@@ -357,12 +357,35 @@ def bench_paper_scheme(td, torch, sched, dev):
             "rows": rows}
 
 
-def time_launches(torch, fn, reps, warmup=3):
+_SLEEP_S_PER_CYCLE = []
+
+
+def _hold_stream(torch, seconds):
+    """Keeps torch's current stream busy for about `seconds` (a spin kernel), so that what the host
+    enqueues meanwhile starts on the GPU back to back, not when the host gets to it."""
+    if not _SLEEP_S_PER_CYCLE:
+        torch.cuda._sleep(1 << 20)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        torch.cuda._sleep(1 << 22)
+        b.record()
+        torch.cuda.synchronize()
+        _SLEEP_S_PER_CYCLE.append(max(a.elapsed_time(b) / 1e3 / (1 << 22), 1e-12))
+    torch.cuda._sleep(min(int(seconds / _SLEEP_S_PER_CYCLE[0]), 1 << 40))
+
+
+def time_launches(torch, fn, reps, warmup=3, hold=True):
     """Mean duration of `fn` (one or more launches on torch's current stream) from HIP events recorded
-    on that stream around each call, in seconds."""
+    on that stream around each call, in seconds.  hold: the stream is held by a spin kernel while the
+    calls are enqueued, so each pair of events brackets the launch as the GPU runs it; without it, a
+    short launch's pair also brackets the host's time to issue it (the GPU reaches the first event
+    before the host has launched the kernel)."""
     for _ in range(warmup):
         fn()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    torch.cuda.synchronize()
+    if hold:
+        _hold_stream(torch, 1e-3 + 40e-6 * reps)
     for a, b in ev:
         a.record()
         fn()
@@ -373,8 +396,10 @@ def time_launches(torch, fn, reps, warmup=3):
 
 def bench_c1(td, torch, inputs, dev, ops_per_block, reps=200):
     """C1: one 1 MiB message (2^17 blocks), one 3-key triple, encrypt then decrypt the ciphertext on one
-    stream, in and out distinct.  Kernel-only: HIP events around each launch; also the back-to-back rate
-    of whole steps (wall time over many steps), which includes the launch gaps."""
+    stream, in and out distinct.  Kernel-only: HIP events around each launch, enqueued while the stream
+    is held (encrypt_us_with_issue: the same without holding it, which adds the host's time to issue
+    a launch); also the back-to-back rate of whole steps (wall time over many steps), which includes
+    the launch gaps."""
     n = 1 << 17
     keys = inputs.key_triple(inputs.KEY_SEED_BASE + 0)
     sched = torch.empty(td.TDES_SCHED_BYTES, dtype=torch.uint8, device=dev)
@@ -387,6 +412,8 @@ def bench_c1(td, torch, inputs, dev, ops_per_block, reps=200):
                     ("bitslice", td.TDES_VARIANT_BITSLICE)):
         enc = time_launches(torch, lambda: td.tdes_ecb_run(sched, src, ct, n, td.TDES_ENCRYPT, v), reps)
         dec = time_launches(torch, lambda: td.tdes_ecb_run(sched, ct, pt, n, td.TDES_DECRYPT, v), reps)
+        enc_issue = time_launches(torch, lambda: td.tdes_ecb_run(sched, src, ct, n, td.TDES_ENCRYPT, v), reps,
+                                  hold=False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(reps):
@@ -396,6 +423,7 @@ def bench_c1(td, torch, inputs, dev, ops_per_block, reps=200):
         step = (time.perf_counter() - t0) / reps
         kernel_s = (enc + dec) / 2
         out[name] = {"encrypt_us": round(enc * 1e6, 2), "decrypt_us": round(dec * 1e6, 2),
+                     "encrypt_us_with_issue": round(enc_issue * 1e6, 2),
                      "gbs": round(n * 8 / kernel_s / 1e9, 3),
                      "step_us_back_to_back": round(step * 1e6, 2),
                      "alu_frac": round(ops_per_block * n / kernel_s / 1e12 / ALU_PEAK_TOPS, 4),
