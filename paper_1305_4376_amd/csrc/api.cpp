@@ -58,9 +58,10 @@ int check_buffers(const void *dev_sched, const void *in, const void *out, uint64
 // The automatic choice, on MI355X measurements of one launch (encrypt, HIP
 // events around the launch): the bitsliced kernel costs about 36 us for
 // anything up to 2^18 blocks (one wave runs a whole 2048-block tile through all
-// 48 rounds) and then scales at about 900 GB/s; the table kernel costs 10-12 us
-// up to 2^16 blocks (14 us at 2^18) and scales at about 260 GB/s.  At 2^20
-// blocks the bitsliced kernel is already ahead (39 vs 42 us).
+// 48 rounds) and then scales at about 900 GB/s; the table kernel costs 8-13 us
+// up to 2^16 blocks (14 us at 2^18; the spread is the launch cost of different
+// machines) and scales at about 260 GB/s.  At 2^20 blocks the bitsliced kernel
+// is already ahead (39 vs 42 us).
 int resolve_variant(int variant, uint64_t n_blocks) {
     if (variant == TDES_VARIANT_AUTO) return n_blocks < tdes::kAutoTableBelow ? TDES_VARIANT_TABLE : TDES_VARIANT_BITSLICE;
     return variant;
