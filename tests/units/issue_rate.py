@@ -4,8 +4,10 @@
 
 For each instruction kind of the bitsliced kernel (two-source XOR and add,
 shifts, v_bitop3_b32 with its three sources in three register banks or two of
-them in one bank, v_perm_b32, and v_bitop3_b32 chains in which each instruction
-reads the result of the one 1, 2, 3, 4 or 8 before it), the probe in k_units.hip runs streams of
+them in one bank, v_perm_b32, v_bitop3_b32 chains in which each instruction
+reads the result of the one 1, 2, 3, 4 or 8 before it, and the round's scalar
+operand forms: a scalar key mask as a v_bitop3_b32 or v_xor_b32 source, and a
+scalar bit-field extract per five v_bitop3_b32), the probe in k_units.hip runs streams of
 independent instructions (blocks of 128 between the loop's scalar branch)
 at 1, 2, 4 and 8 waves per SIMD (256-thread
 workgroups, compute-unit count x waves workgroups).  Each wave records the
@@ -36,7 +38,9 @@ OPS = ["v_xor_b32", "v_add_u32", "v_lshrrev_b32", "v_lshlrev_b32", "v_bitop3_b32
        "v_bitop3_b32 chain, each on the one 2 before", "v_bitop3_b32 chain, each on the one 4 before",
        "v_bitop3_b32 chain, each on the one 3 before", "v_bitop3_b32 chain, each on the one 8 before",
        "v_bitop3_b32 chain, each on the one 4 before, results in rotating banks",
-       "v_bitop3_b32, sources in banks 0, 1, 2, result in bank 3", "v_bitop3_b32, sources in banks 0, 1, 2, result in bank 0"]
+       "v_bitop3_b32, sources in banks 0, 1, 2, result in bank 3", "v_bitop3_b32, sources in banks 0, 1, 2, result in bank 0",
+       "v_bitop3_b32 with a scalar third source", "v_xor_b32 with a scalar first source",
+       "s_bfe_i32 then five v_bitop3_b32, the first reading its result (counted: VALU only)"]
 NOMINAL_HZ = 2.4e9
 
 
@@ -72,7 +76,7 @@ def main():
             assert rc == 0
             wall = start.elapsed_time(stop) / 1e3
             c = clk.cpu().numpy().reshape(-1, 6)
-            instr = 128.0 * args.iters
+            instr = (640.0 if op == 17 else 128.0) * args.iters   # VALU instructions per wave
             simd = (c[:, 5] << 16) | (c[:, 4] & 0xFF30)  # XCC, SE, SH, CU, SIMD
             rates, counts = [], []
             for key in np.unique(simd):

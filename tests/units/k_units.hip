@@ -137,6 +137,20 @@ __global__ void folded_stage_kernel(const uint32_t *blocks, const uint32_t *dir_
 // Independent v_bitop3_b32 with sources in banks 0, 1, 2 and the result in bank 3 or in bank 0.
 #define PROBE_DST3 "v_bitop3_b32 v11, v24, v37, v46 bitop3:0x96\n" "v_bitop3_b32 v15, v28, v41, v50 bitop3:0x96\n" "v_bitop3_b32 v19, v32, v45, v54 bitop3:0x96\n" "v_bitop3_b32 v23, v36, v49, v26 bitop3:0x96\n" "v_bitop3_b32 v11, v40, v53, v30 bitop3:0x96\n" "v_bitop3_b32 v15, v44, v25, v34 bitop3:0x96\n" "v_bitop3_b32 v19, v48, v29, v38 bitop3:0x96\n" "v_bitop3_b32 v23, v52, v33, v42 bitop3:0x96\n" "v_bitop3_b32 v11, v24, v37, v46 bitop3:0x96\n" "v_bitop3_b32 v15, v28, v41, v50 bitop3:0x96\n" "v_bitop3_b32 v19, v32, v45, v54 bitop3:0x96\n" "v_bitop3_b32 v23, v36, v49, v26 bitop3:0x96\n" "v_bitop3_b32 v11, v40, v53, v30 bitop3:0x96\n" "v_bitop3_b32 v15, v44, v25, v34 bitop3:0x96\n" "v_bitop3_b32 v19, v48, v29, v38 bitop3:0x96\n" "v_bitop3_b32 v23, v52, v33, v42 bitop3:0x96\n"
 #define PROBE_DST0 "v_bitop3_b32 v8, v24, v37, v46 bitop3:0x96\n" "v_bitop3_b32 v12, v28, v41, v50 bitop3:0x96\n" "v_bitop3_b32 v16, v32, v45, v54 bitop3:0x96\n" "v_bitop3_b32 v20, v36, v49, v26 bitop3:0x96\n" "v_bitop3_b32 v8, v40, v53, v30 bitop3:0x96\n" "v_bitop3_b32 v12, v44, v25, v34 bitop3:0x96\n" "v_bitop3_b32 v16, v48, v29, v38 bitop3:0x96\n" "v_bitop3_b32 v20, v52, v33, v42 bitop3:0x96\n" "v_bitop3_b32 v8, v24, v37, v46 bitop3:0x96\n" "v_bitop3_b32 v12, v28, v41, v50 bitop3:0x96\n" "v_bitop3_b32 v16, v32, v45, v54 bitop3:0x96\n" "v_bitop3_b32 v20, v36, v49, v26 bitop3:0x96\n" "v_bitop3_b32 v8, v40, v53, v30 bitop3:0x96\n" "v_bitop3_b32 v12, v44, v25, v34 bitop3:0x96\n" "v_bitop3_b32 v16, v48, v29, v38 bitop3:0x96\n" "v_bitop3_b32 v20, v52, v33, v42 bitop3:0x96\n"
+// The round's operand forms: v_bitop3_b32 with a scalar register as its third source (the output
+// XORs with their key mask), v_xor_b32 with a scalar first source (the input corrections), and the
+// round's mix of one scalar bit-field extract (its result read by the next v_bitop3) per five
+// v_bitop3 (s4, s5: any value).
+#define P_BITOP3_S(D, A, B, C, A2) "v_bitop3_b32 v" #D ", v" #A ", v" #B ", s4 bitop3:0x96\n"
+#define P_XOR_S(D, A, B, C, A2) "v_xor_b32 v" #D ", s4, v" #A "\n"
+#define P_BFE_MIX(D, A, B, C, A2) "s_bfe_i32 s72, s5, 0x10003\n" "v_bitop3_b32 v" #D ", v" #A ", v" #B ", s72 bitop3:0x96\n" \
+    "v_bitop3_b32 v" #D ", v" #A ", v" #B ", v" #C " bitop3:0x96\n" "v_bitop3_b32 v" #D ", v" #A ", v" #B ", v" #C " bitop3:0x69\n" \
+    "v_bitop3_b32 v" #D ", v" #A ", v" #B ", v" #C " bitop3:0x5a\n" "v_bitop3_b32 v" #D ", v" #A ", v" #B ", v" #C " bitop3:0xa5\n"
+#define PROBE_CLOBBERS_S PROBE_CLOBBERS, "s72", "scc"
+#define PROBE_CASE_S(K, M)                                                                 \
+    case K:                                                                                \
+        for (int i = 0; i < iters; i++) asm volatile(PROBE_BLOCK(M)::: PROBE_CLOBBERS_S);  \
+        break;
 #define PROBE_CLOBBERS                                                                                       \
     "v8", "v9", "v10", "v11", "v12", "v13", "v14", "v15", "v16", "v17", "v18", "v19", "v20", "v21", "v22", "v23", \
         "v24", "v25", "v26", "v27", "v28", "v29", "v30", "v31", "v32", "v33", "v34", "v35", "v36", "v37", "v38",   \
@@ -175,6 +189,9 @@ __global__ __launch_bounds__(256) void issue_probe_kernel(int op, int iters, uin
         PROBE_CHAIN_CASE(12, PROBE_CHAIN4R)
         PROBE_CHAIN_CASE(13, PROBE_DST3)
         PROBE_CHAIN_CASE(14, PROBE_DST0)
+        PROBE_CASE(15, P_BITOP3_S)
+        PROBE_CASE(16, P_XOR_S)
+        PROBE_CASE_S(17, P_BFE_MIX)
         default:
             break;
     }
@@ -232,7 +249,7 @@ __global__ __launch_bounds__(256, 4) void rounds_probe_kernel(int iters, uint32_
 
 // groups workgroups of 256 threads; dev_clk holds 6 * 4 * groups words.
 extern "C" int units_issue_probe(int op, int groups, int iters, uint64_t *dev_clk) {
-    if (op < 0 || op > 14 || groups < 1 || iters < 1) return -1;
+    if (op < 0 || op > 17 || groups < 1 || iters < 1) return -1;
     hipLaunchKernelGGL(issue_probe_kernel, dim3(groups), dim3(256), 0, 0, op, iters, dev_clk);
     return status();
 }
